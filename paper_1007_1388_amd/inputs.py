@@ -1,0 +1,181 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds no lattice Boltzmann arithmetic: it only draws geometries
+(solid masks), block tilings and random perturbation fields from numpy's
+PCG64 generator, so the GPU library and the CPU oracle can be fed the very
+same data.
+
+Workload shapes follow the paper's synthetic scenarios: lid-driven cavities
+(Sec. 5), single-Block cubes and domains split into a Cartesian grid of
+Blocks (Sec. 4.2, Sec. 5.1), extended with the channel, porous-channel and
+precision presets the benchmark uses.
+"""
+import numpy as np
+
+
+# ----------------------------------------------------------- geometries -----
+
+def porous_spheres(dims, target_fraction=0.10, radius=(3, 8), seed=0,
+                   periodic=(True, True, False)):
+    """Random spheres until the solid fraction reaches ``target_fraction``.
+
+    dims = (nx, ny, nz); returns uint8 [nz, ny, nx], 1 = solid.  Centres are
+    uniform in the domain, radii are integers uniform in [radius[0],
+    radius[1]]; a cell is solid when its centre lies within the radius of a
+    sphere, taking periodic images on the axes flagged ``periodic``.
+    """
+    nx, ny, nz = (int(d) for d in dims)
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    n = [nx, ny, nz]
+    target = float(target_fraction) * solid.size
+    if target <= 0:
+        return solid.astype(np.uint8)
+    for _ in range(100000):
+        c = rng.uniform(0, 1, 3) * np.array(n)
+        r = int(rng.integers(radius[0], radius[1] + 1))
+        d2 = np.zeros(solid.shape)
+        for axis, coord in enumerate((xx, yy, zz)):
+            diff = np.abs(coord - c[axis])
+            if periodic[axis]:
+                diff = np.minimum(diff, n[axis] - diff)
+            d2 = d2 + diff * diff
+        solid |= d2 <= r * r
+        if solid.sum() >= target:
+            break
+    return solid.astype(np.uint8)
+
+
+def channel_obstacle(dims, center=None, radius=3):
+    """One sphere obstacle in a channel (deterministic), uint8 [nz, ny, nx]."""
+    nx, ny, nz = dims
+    c = center if center is not None else (nx / 2 - 0.5, ny / 2 - 0.5, nz / 2 - 0.5)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d2 = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2
+    return (d2 <= radius * radius).astype(np.uint8)
+
+
+# --------------------------------------------------------------- tilings ----
+
+def uniform_blocks(dims, counts):
+    """Cartesian grid of near-equal Blocks: counts = (bx, by, bz).
+
+    Returns a list of (lo, hi) half-open cell boxes in BlockID order (x
+    fastest), like the paper's Patch split into a Cartesian grid of Blocks
+    (Sec. 4.2).
+    """
+    cuts = []
+    for n, k in zip(dims, counts):
+        edges = [round(j * n / k) for j in range(k + 1)]
+        cuts.append(edges)
+    return _product(cuts)
+
+
+def segments(length, choices, rng, max_tries=10000):
+    """Split ``length`` into segments drawn uniformly from ``choices``.
+
+    Draws until the running sum reaches ``length``; accepts if it is exact,
+    otherwise redraws from scratch.
+    """
+    for _ in range(max_tries):
+        out, s = [], 0
+        while s < length:
+            v = int(rng.choice(choices))
+            out.append(v)
+            s += v
+        if s == length:
+            return out
+    raise ValueError("no exact split of %d from %s" % (length, choices))
+
+
+def uneven_blocks(dims, choices=(32, 48, 64), seed=0):
+    """Seeded uneven Cartesian tiling: per axis, segments from ``choices``.
+
+    The Blocks are the Cartesian product of the three axis splits, so every
+    face and edge neighbour is unique (a rectilinear grid of Blocks).
+    """
+    rng = np.random.default_rng(seed)
+    cuts = []
+    for n in dims:
+        seg = segments(n, choices, rng)
+        cuts.append([0] + list(np.cumsum(seg)))
+    return _product(cuts)
+
+
+def uneven_blocks_grid(counts=(4, 4, 4), choices=(32, 48, 64), seed=0):
+    """Exactly bx*by*bz Blocks with per-axis edge lengths drawn from ``choices``;
+    the domain is whatever the lengths sum to.  Returns (dims, blocks)."""
+    rng = np.random.default_rng(seed)
+    cuts, dims = [], []
+    for k in counts:
+        seg = [int(rng.choice(choices)) for _ in range(k)]
+        cuts.append([0] + list(np.cumsum(seg)))
+        dims.append(int(sum(seg)))
+    return tuple(dims), _product(cuts)
+
+
+def _product(cuts):
+    blocks = []
+    cx, cy, cz = cuts
+    for k in range(len(cz) - 1):
+        for j in range(len(cy) - 1):
+            for i in range(len(cx) - 1):
+                blocks.append(((int(cx[i]), int(cy[j]), int(cz[k])),
+                               (int(cx[i + 1]), int(cy[j + 1]), int(cz[k + 1]))))
+    return blocks
+
+
+def random_tiling(dims, max_blocks_per_axis=3, seed=0, min_edge=1):
+    """Random rectilinear tiling with arbitrary (possibly tiny) edges."""
+    rng = np.random.default_rng(seed)
+    cuts = []
+    for n in dims:
+        k = int(rng.integers(1, max_blocks_per_axis + 1))
+        k = min(k, n // min_edge)
+        inner = sorted(rng.choice(np.arange(min_edge, n - min_edge + 1), size=k - 1,
+                                  replace=False).tolist()) if k > 1 else []
+        edges = [0] + inner + [n]
+        # enforce the minimum edge
+        ok = all(b - a >= min_edge for a, b in zip(edges[:-1], edges[1:]))
+        cuts.append(edges if ok else [0, n])
+    return _product(cuts)
+
+
+# ------------------------------------------------------- random fields ------
+
+def perturbed_fields(dims, seed=0, drho=1e-3, du=1e-2, rho0=1.0):
+    """Random (rho, u) fields: rho [nz,ny,nx], u [3,nz,ny,nx], FP64."""
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    rho = rho0 + drho * rng.standard_normal((nz, ny, nx))
+    u = du * rng.standard_normal((3, nz, ny, nx))
+    return rho, u
+
+
+# ---------------------------------------------------------------- presets ---
+
+def preset(name):
+    """Named workloads (dicts of plain parameters, no arithmetic).
+
+    cavity32      32^3 lid-driven cavity, FP64, tau 0.6, lid (0.05,0,0) on +z
+    poiseuille256 256^3 channel, periodic x,y, walls z, g_x 1e-6, tau 0.8
+    porous512     512x256x256 porous channel, uneven {32,48,64} Blocks,
+                  spheres r 3..8 to 10 % solid, tau 0.7, g_x 1e-6
+    cavity384     384^3 cavity, tau 0.55, lid (0.1,0,0)
+    warmstart     64x64x128 porous channel, tau 0.7 (surrogate data)
+    """
+    p = {
+        "cavity32": dict(dims=(32, 32, 32), walls=(True, True, True), tau=0.6,
+                         wall_u={"+z": (0.05, 0.0, 0.0)}, force=(0.0, 0.0, 0.0), steps=100),
+        "poiseuille256": dict(dims=(256, 256, 256), walls=(False, False, True), tau=0.8,
+                              wall_u={}, force=(1e-6, 0.0, 0.0), steps=2000),
+        "porous512": dict(dims=(512, 256, 256), walls=(False, False, True), tau=0.7,
+                          wall_u={}, force=(1e-6, 0.0, 0.0), steps=1000,
+                          solid_fraction=0.10, radius=(3, 8), block_edges=(32, 48, 64)),
+        "cavity384": dict(dims=(384, 384, 384), walls=(True, True, True), tau=0.55,
+                          wall_u={"+z": (0.1, 0.0, 0.0)}, force=(0.0, 0.0, 0.0), steps=5000),
+        "warmstart": dict(dims=(64, 64, 128), walls=(False, False, True), tau=0.7,
+                          wall_u={}, solid_fraction=(0.05, 0.20), force_range=(5e-7, 5e-6)),
+    }
+    return dict(p[name])

@@ -1,0 +1,293 @@
+"""Pins of the CPU FP64 oracle against what the mathematics fixes.
+
+Nothing here compares the oracle with itself or with a retyped copy of its
+update formula: every expected value is a closed form, an invariant, a
+symmetry or a special case with a textbook answer.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1007_1388_amd import inputs
+
+E = oracle.velocities()
+W = oracle.weights()
+
+
+# ---------------------------------------------------------------- stencil ---
+
+def test_stencil_is_d3q19():
+    # 19 distinct velocities: the rest vector, 6 faces and 12 edges (Sec. 2.1)
+    assert len({tuple(e) for e in E}) == 19
+    sq = (E ** 2).sum(1)
+    assert sorted(sq.tolist()) == [0] + [1] * 6 + [2] * 12
+    assert np.abs(E).max() == 1
+    # closed under negation
+    for e in E:
+        assert any((E == -e).all(1))
+
+
+def test_weights_moments_are_isotropic():
+    # Lattice-tensor identities that make the equilibrium of Eq. (2) carry
+    # density, momentum and the isotropic stress of a c_s^2 = 1/3 gas.
+    assert W.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.abs((W[:, None] * E).sum(0)).max() < 1e-16
+    m2 = np.einsum("i,ia,ib->ab", W, E, E)
+    assert np.abs(m2 - np.eye(3) / 3).max() < 1e-15
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", W, E, E, E, E)
+    d = np.eye(3)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(m4 - iso).max() < 1e-15
+    # third moment vanishes (symmetric set)
+    assert np.abs(np.einsum("i,ia,ib,ic->abc", W, E, E, E)).max() < 1e-16
+
+
+# ------------------------------------------------------- fixed points -------
+
+def test_rest_state_with_walls_is_fixed():
+    o = oracle.OracleLBM((5, 4, 6), walls=(True, True, True), tau=0.7)
+    o.step(20)
+    assert np.abs(o.get_state()).max() == 0.0
+    rho, u = o.macroscopic()
+    assert np.all(rho == 1.0) and np.all(u == 0.0)
+
+
+@pytest.mark.parametrize("tau", [0.52, 0.8, 1.7])
+def test_uniform_equilibrium_is_fixed(tau):
+    # A uniform equilibrium in a periodic box has no gradients: streaming
+    # leaves it unchanged and the collision returns it (Eq. 1 with f = feq).
+    dims = (4, 3, 5)
+    o = oracle.OracleLBM(dims, tau=tau)
+    shape = (5, 3, 4)
+    rho = np.full(shape, 1.0 + 3e-3)
+    u = np.empty((3,) + shape)
+    u[0], u[1], u[2] = 0.04, -0.02, 0.01
+    o.set_equilibrium(rho, u)
+    f0 = o.get_state()
+    o.step(10)
+    assert np.abs(o.get_state() - f0).max() < 1e-13 * np.abs(f0).max()
+    r, v = o.macroscopic()
+    assert np.abs(r - rho).max() < 1e-15
+    assert np.abs(v - u).max() < 1e-16
+
+
+# ---------------------------------------------------------- streaming -------
+
+@pytest.mark.parametrize("i", range(1, 19))
+def test_free_streaming_moves_each_population_along_its_velocity(i):
+    # With tau -> infinity the collision vanishes (omega ~ 1e-13) and a lone
+    # population of direction i must travel one cell per step along e_i, with
+    # periodic wrap (pull streaming, Sec. 2.1).
+    dims = (5, 6, 7)
+    o = oracle.OracleLBM(dims, tau=1e13)
+    f = np.zeros((19, 7, 6, 5))
+    x0 = np.array([1, 4, 6])  # (x, y, z), next to several faces
+    f[i, x0[2], x0[1], x0[0]] = 1e-3
+    o.set_state(f)
+    for t in range(1, 4):
+        o.step(1)
+        g = o.get_state()
+        p = (x0 + t * E[i]) % np.array(dims)
+        assert g[i, p[2], p[1], p[0]] == pytest.approx(1e-3, rel=1e-9)
+        g[i, p[2], p[1], p[0]] = 0.0
+        assert np.abs(g).max() < 1e-14
+
+
+# -------------------------------------------------------- conservation ------
+
+def _perturbed_state(o, seed, amp=1e-3):
+    rng = np.random.default_rng(seed)
+    shape = o.shape
+    rho = 1.0 + amp * rng.standard_normal(shape)
+    u = 10 * amp * rng.standard_normal((3,) + shape)
+    o.set_equilibrium(rho, u)
+
+
+def test_periodic_box_conserves_mass_and_gains_force_momentum():
+    # Streaming permutes populations and the collision keeps density; the
+    # Guo source adds exactly rho0*g of momentum per cell and step.
+    g = np.array([2e-5, -1e-5, 3e-6])
+    o = oracle.OracleLBM((6, 5, 4), tau=0.73, force=g)
+    _perturbed_state(o, 1)
+    m0, _ = o.sums()
+    o.step(1)
+    _, p_prev = o.sums()
+    n = o.ncell
+    for _ in range(25):
+        o.step(1)
+        m, p = o.sums()
+        assert abs(m - m0) <= 1e-13 * n
+        assert np.abs((p - p_prev) - n * g).max() <= 1e-15 * n
+        p_prev = p
+
+
+def test_obstacles_and_walls_conserve_mass():
+    # Half-way bounce-back returns every population it intercepts.
+    dims = (10, 9, 8)
+    solid = inputs.porous_spheres(dims, target_fraction=0.15, radius=(1, 2), seed=3)
+    o = oracle.OracleLBM(dims, walls=(False, True, True), tau=0.65, force=(1e-5, 0, 0))
+    o.set_geometry(solid)
+    _perturbed_state(o, 2)
+    m0, _ = o.sums()
+    o.step(60)
+    m, _ = o.sums()
+    assert abs(m - m0) < 1e-12 * o.ncell
+
+
+def test_cavity_with_moving_lid_conserves_mass():
+    # The lid correction terms cancel in +/- pairs when every halo cell beyond
+    # the moving face counts as moving (the edge/corner reading).
+    o = oracle.OracleLBM((8, 8, 8), walls=(True, True, True), tau=0.6,
+                         wall_u={"+z": (0.05, 0.0, 0.0)})
+    m0, _ = o.sums()
+    o.step(200)
+    m, p = o.sums()
+    assert abs(m - m0) < 1e-12 * 512
+    assert p[0] > 0  # the lid drags the fluid along +x
+
+
+# ------------------------------------------------------ closed forms --------
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 0.5 + np.sqrt(3) / 4])
+def test_poiseuille_exact_discrete_profile(tau):
+    # Force-driven channel between half-way bounce-back walls.  With Guo
+    # forcing the steady BGK solution is the parabola with K = g/(2 nu),
+    # nu = (tau - 1/2)/3 (Sec. 2.1), plus the known uniform slip
+    # K (16 tau^2 - 16 tau + 1)/12, which vanishes at tau = 1/2 + sqrt(3)/4.
+    nz, g = 16, 1e-6
+    o = oracle.OracleLBM((1, 1, nz), walls=(False, False, True), tau=tau, force=(g, 0, 0))
+    o.step(60000)
+    _, u = o.macroscopic()
+    ux = u[0, :, 0, 0]
+    z = np.arange(nz)
+    K = g / (2 * (tau - 0.5) / 3)
+    s = K * (16 * tau * tau - 16 * tau + 1) / 12
+    ref = K * (z + 0.5) * (nz - 0.5 - z) + s
+    assert np.abs(ux - ref).max() < 1e-9 * ref.max()
+    assert np.abs(u[1:]).max() < 1e-13 * ref.max()
+
+
+def test_couette_exact_linear_profile():
+    # Moving +z wall, resting -z wall: the steady profile is linear with the
+    # no-slip points half a cell outside the fluid (half-way bounce-back,
+    # standard sign of the moving-wall term).
+    nz, U = 8, 0.01
+    o = oracle.OracleLBM((1, 1, nz), walls=(False, False, True), tau=0.8,
+                         wall_u={"+z": (U, 0, 0)})
+    o.step(20000)
+    _, u = o.macroscopic()
+    z = np.arange(nz)
+    assert np.abs(u[0, :, 0, 0] - U * (z + 0.5) / nz).max() < 1e-12 * U
+
+
+def test_shear_wave_decays_at_the_bgk_viscosity():
+    # u_x = U sin(2 pi z / L) in a periodic box decays like exp(-nu k^2 t),
+    # nu = (tau - 1/2)/3 (Sec. 2.1); the lattice correction is O(k^2).
+    L, tau, U = 64, 0.8, 1e-4
+    o = oracle.OracleLBM((1, 1, L), tau=tau)
+    z = np.arange(L)
+    u = np.zeros((3, L, 1, 1))
+    u[0, :, 0, 0] = U * np.sin(2 * np.pi * z / L)
+    o.set_equilibrium(np.ones((L, 1, 1)), u)
+    mode = np.sin(2 * np.pi * z / L)
+
+    def amp():
+        return (o.macroscopic()[1][0, :, 0, 0] * mode).sum() * 2 / L
+
+    o.step(200)
+    a0 = amp()
+    o.step(1000)
+    a1 = amp()
+    nu = (tau - 0.5) / 3
+    k = 2 * np.pi / L
+    rate = -np.log(a1 / a0) / 1000
+    assert rate == pytest.approx(nu * k * k, rel=3e-3)
+    # the residual of one step equals 1 - exp(-rate) for a pure decaying mode
+    o.step(1)
+    assert o.residual() == pytest.approx(1 - np.exp(-rate), rel=3e-3)
+
+
+# ------------------------------------------------------------ symmetry ------
+
+def _cavity(n=(8, 8, 8), lid=(0.05, 0, 0), face="+z", steps=200):
+    o = oracle.OracleLBM(n, walls=(True, True, True), tau=0.6, wall_u={face: lid})
+    o.step(steps)
+    return o.macroscopic()
+
+
+def test_cavity_mirror_symmetry():
+    # Lid along +x: the geometry is symmetric under y -> ny-1-y, so u_x, u_z
+    # are even and u_y odd about the mid-plane.
+    rho, u = _cavity()
+    flip = lambda a: a[:, ::-1, :]
+    assert np.abs(u[0] - flip(u[0])).max() < 1e-15
+    assert np.abs(u[2] - flip(u[2])).max() < 1e-15
+    assert np.abs(u[1] + flip(u[1])).max() < 1e-15
+    assert np.abs(rho - flip(rho)).max() < 1e-15
+    assert np.abs(u).max() > 1e-3
+
+
+def test_cavity_axis_permutation_equivariance():
+    # Swapping the roles of x and y (lid along +y) must give the transposed
+    # field: checks that no direction index is special.
+    _, ua = _cavity(lid=(0.05, 0, 0))
+    _, ub = _cavity(lid=(0, 0.05, 0))
+    # ub(x, y) == swap(ua)(y, x): arrays are (z, y, x)
+    assert np.abs(ub[1] - ua[0].transpose(0, 2, 1)).max() < 1e-15
+    assert np.abs(ub[0] - ua[1].transpose(0, 2, 1)).max() < 1e-15
+    assert np.abs(ub[2] - ua[2].transpose(0, 2, 1)).max() < 1e-15
+
+
+def test_lid_on_each_face_gives_rotated_field():
+    # The cavity driven from the -x face with the lid moving along +z is the
+    # +z-lid cavity rotated about y; pins the face order and the wall-velocity
+    # lookup.  Rotation: point (x, y, z) -> (n-1-z, y, x), so the +z face maps
+    # to the -x face, and vector (vx, vy, vz) -> (-vz, vy, vx).
+    _, ua = _cavity(lid=(0.05, 0, 0), face="+z")
+    _, ub = _cavity(lid=(0, 0, 0.05), face="-x")
+    n = 8
+    for z, y, x in itertools.product(range(n), range(n), range(n)):
+        xb, yb, zb = n - 1 - z, y, x
+        va = ua[:, z, y, x]
+        vb = ub[:, zb, yb, xb]
+        assert abs(vb[0] + va[2]) < 1e-15
+        assert abs(vb[1] - va[1]) < 1e-15
+        assert abs(vb[2] - va[0]) < 1e-15
+
+
+# --------------------------------------------------- bookkeeping ------------
+
+def test_macroscopic_before_any_step_is_the_initial_field():
+    o = oracle.OracleLBM((3, 4, 5), tau=0.9)
+    rng = np.random.default_rng(0)
+    rho = 1 + 1e-3 * rng.standard_normal((5, 4, 3))
+    u = 1e-2 * rng.standard_normal((3, 5, 4, 3))
+    o.set_equilibrium(rho, u)
+    r, v = o.macroscopic()
+    assert np.array_equal(r, rho) and np.array_equal(v, u)
+    m, p = o.sums()
+    assert m == pytest.approx(rho.sum(), rel=1e-15)
+    assert np.abs(p - u.reshape(3, -1).sum(1)).max() < 1e-15
+
+
+def test_solid_cells_report_rest_and_hold_zero():
+    dims = (6, 6, 6)
+    solid = np.zeros((6, 6, 6), np.uint8)
+    solid[2:4, 2:4, 2:4] = 1
+    o = oracle.OracleLBM(dims, tau=0.7, force=(1e-4, 0, 0))
+    o.set_geometry(solid)
+    o.step(30)
+    rho, u = o.macroscopic()
+    assert np.all(rho[solid == 1] == 1.0) and np.all(u[:, solid == 1] == 0.0)
+    assert np.all(o.get_state()[:, solid == 1] == 0.0)
+    assert np.abs(u[0][solid == 0]).max() > 0
+
+
+def test_invalid_parameters_rejected():
+    with pytest.raises(ValueError):
+        oracle.OracleLBM((4, 4, 4), tau=0.5)
+    with pytest.raises(ValueError):
+        oracle.OracleLBM((0, 4, 4), tau=0.7)

@@ -1,0 +1,175 @@
+"""Benchmark: D3Q19 BGK stream-collide throughput on one MI355X.
+
+Default workload: the force-driven plane Poiseuille channel, 256^3 cells,
+periodic in x and y, half-way bounce-back walls in z, g_x = 1e-6, tau = 0.8,
+started from rest, FP32 storage (and FP64 beside it).  One step = one sweep of
+every Block (pull, bounce-back, collision, fused ghost exchange) over the
+whole domain.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1007_1388_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name, src_hash):
+    """HBM bytes per sweep launch from committed rocprofv3 counter summaries,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(PROFILE_DIR, name)
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def workload(name):
+    from paper_1007_1388_amd import inputs
+    p = inputs.preset(name)
+    blocks = None
+    solid = None
+    if name == "porous512":
+        blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
+        solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
+    return p, blocks, solid
+
+
+def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=None):
+    import torch
+    from paper_1007_1388_amd import lbm
+    lat = lbm.Lattice(p["dims"], blocks=blocks, walls=p["walls"], wall_u=p["wall_u"], tau=p["tau"],
+                      force=p["force"], precision=precision, fp64_math=fp64_math)
+    if solid is not None:
+        lat.set_geometry(solid)
+    if schedule:
+        lat.set_schedule(**schedule)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    info = lat.info()
+    sched = lat.schedule
+    mass, _ = lat.sums()   # finite-check of the run (raises on instability)
+    lat.close()
+    return dict(wall=wall, kernel_ms=gpu_ms / steps, info=info, schedule=sched, mass=mass)
+
+
+def cpu_baseline(p, solid, seconds=15.0):
+    """The CPU FP64 oracle on the host cores, on a bounded sample of the same
+    workload (the full domain for as many steps as fit in ~seconds)."""
+    import oracle
+    o = oracle.OracleLBM(p["dims"], walls=p["walls"], wall_u=p["wall_u"], tau=p["tau"], force=p["force"])
+    if solid is not None:
+        o.set_geometry(solid)
+    o.step(1)  # touch memory
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        o.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    cells = o.ncell if solid is None else int((solid == 0).sum())
+    o.close()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=round(cells * n / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+                sample="%s full domain %s, %d steps after 1 warm-up, FP64, %d OpenMP threads"
+                       % ("x".join(map(str, p["dims"])), "porous" if solid is not None else "",
+                          n, cores))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="poiseuille256",
+                    choices=["poiseuille256", "porous512", "cavity384", "cavity32"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
+    ap.add_argument("--fp64-math", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the Block exchange between GPUs is a "
+              "design, not code); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.init()
+    p, blocks, solid = workload(args.workload)
+    prec = args.precision
+    f64m = bool(args.fp64_math) and prec in ("f32", "f64")
+    r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup)
+    info = r["info"]
+    nf = info["n_fluid"]
+    mlups = nf * args.steps / r["wall"] / 1e6
+    bpu = info["bytes_per_update"]
+    achieved = nf * bpu / (r["kernel_ms"] * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    tr = traffic_from_profile("sweep_%s_%s_pmc.json" % (prec, args.workload), src_hash)
+    out = {
+        "metric": "D3Q19 MLUPS (fluid lattice-cell updates per second, millions)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": ("f64" if (prec == "f64" or f64m) else "f32"),
+        "data": "synthetic",
+        "config": {"workload": "%s %s" % (args.workload, "x".join(map(str, p["dims"]))),
+                   "storage": prec, "arithmetic": "f64" if (prec == "f64" or f64m) else "f32",
+                   "tau": p["tau"], "force": list(p["force"]), "blocks": info["n_blocks"],
+                   "fluid_cells": nf, "schedule": r["schedule"], "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (round(tr / (r["kernel_ms"] * 1e-3) / 1e9, 1) if tr else None),
+                     "kernel": "k_sweep", "kernel_ms": round(r["kernel_ms"], 5),
+                     "bytes_per_update": bpu, "kernel_hash": src_hash},
+    }
+    if not args.no_f64 and prec == "f32":
+        r64 = time_gpu(p, blocks, solid, "f64", False, max(1, args.steps // 2), args.warmup)
+        i64 = r64["info"]
+        m64 = i64["n_fluid"] * max(1, args.steps // 2) / r64["wall"] / 1e6
+        a64 = i64["n_fluid"] * i64["bytes_per_update"] / (r64["kernel_ms"] * 1e-3) / 1e9
+        out["f64_storage"] = {"value": round(m64, 1), "unit": "MLUPS", "steps": max(1, args.steps // 2),
+                              "roofline_frac": round(a64 / HBM_PEAK_GBS, 4), "achieved_gbs": round(a64, 1),
+                              "kernel_ms": round(r64["kernel_ms"], 5)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, solid)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

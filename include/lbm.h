@@ -1,0 +1,191 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) patch-and-block D3Q19 lattice
+ * Boltzmann library.
+ *
+ * The method is the one of Feichtinger et al., "A Flexible Patch-Based Lattice
+ * Boltzmann Parallelization Approach for Heterogeneous GPU-CPU Clusters":
+ *   - D3Q19 BGK with the incompressible equilibrium of Eq. (2), populations
+ *     stored shifted by w_i rho0 (Sec. 2.1);
+ *   - pull streaming over two grids, SoA layout (Sec. 2.1, Sec. 3.2);
+ *   - half-way bounce-back walls with an optional wall velocity (Sec. 2.1);
+ *   - one Patch split into a Cartesian grid of Blocks, each with an
+ *     axis-aligned bounding box and a BlockID (Sec. 4.2);
+ *   - a time step is one Sweep: the ghost-layer exchange between Blocks plus
+ *     the stream-collide kernel over every Block (Sec. 4, Sec. 4.4).
+ * A body force (Guo forcing, u = j/rho0 + g/2) extends the method for
+ * force-driven channels; with g = 0 it reduces exactly to the plain method.
+ *
+ * Conventions
+ *   - Every call returns lbm_status.  No C++ exception crosses the ABI.
+ *   - Cell arrays are global, x fastest: index c = (z*ny + y)*nx + x.
+ *     Vector fields are SoA: u[a*N + c], a = 0,1,2.  Population arrays are
+ *     [i][z][y][x] with the direction order
+ *       0:(0,0,0) 1:(+1,0,0) 2:(-1,0,0) 3:(0,+1,0) 4:(0,-1,0) 5:(0,0,+1)
+ *       6:(0,0,-1) 7:(+1,+1,0) 8:(-1,-1,0) 9:(+1,-1,0) 10:(-1,+1,0)
+ *       11:(+1,0,+1) 12:(-1,0,-1) 13:(+1,0,-1) 14:(-1,0,+1) 15:(0,+1,+1)
+ *       16:(0,-1,-1) 17:(0,+1,-1) 18:(0,-1,+1).
+ *   - Walls lie half a cell outside the outermost cells of a WALL face.
+ *   - Ownership: the context owns all device memory it allocates (through
+ *     dev_alloc/dev_free when given, else hipMalloc/hipFree).  The caller
+ *     owns every buffer it passes; none is retained after a call returns.
+ *   - Ordering: work is enqueued on params.stream.  lbm_step is
+ *     asynchronous; lbm_macroscopic, lbm_residual, lbm_sums, lbm_get_state
+ *     and lbm_info synchronise that stream.
+ *   - Errors: on LBM_EINVAL / LBM_ENOMEM the context is unchanged.
+ *     LBM_EUNSTABLE is returned by a synchronising call that finds a
+ *     non-finite FP64 sum; the state is then undefined.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = 1,    /* bad argument: parameters, tiling, sizes, NULL pointers */
+  LBM_ENOMEM = 2,    /* device or host allocation failed */
+  LBM_EDEVICE = 3,   /* a HIP call failed (message in lbm_last_error) */
+  LBM_ESTATE = 4,    /* call not valid in the current state */
+  LBM_EUNSTABLE = 5  /* non-finite values found by a reduction */
+} lbm_status;
+
+/* Storage precision of the populations.  F16S/BF16S store the shifted
+ * values f~ = f - w_i rho0 (Sec. 2.1) in 16 bits, converted with
+ * round-to-nearest-even, and always compute in FP32. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_precision;
+
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face;
+
+/* Half-open global cell box [lo, hi) of one Block (the Block AABB, Sec. 4.2). */
+typedef struct { int32_t lo[3], hi[3]; } lbm_aabb;
+
+typedef struct {
+  int32_t dims[3];        /* nx, ny, nz of the single Patch, each >= 1 */
+  int32_t face[6];        /* lbm_face of -x,+x,-y,+y,-z,+z; opposite faces must match */
+  double wall_u[6][3];    /* wall velocity per face; its normal component must be 0,
+                             and it must be 0 on PERIODIC faces */
+  double tau;             /* BGK relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
+  double rho0;            /* reference density, > 0 (1 for all presets) */
+  double force[3];        /* body force g per unit mass, lattice units */
+  int32_t precision;      /* lbm_precision */
+  int32_t fp64_math;      /* 1: FP64 arithmetic (F64 and F32 storage); F16S/BF16S ignore it */
+  void* stream;           /* hipStream_t; NULL = the null stream */
+  void* (*dev_alloc)(size_t bytes, void* user);  /* optional device allocator */
+  void (*dev_free)(void* ptr, void* user);
+  void* alloc_user;
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Kernel schedule of a context: how the Blocks are cut into work items and
+ * launched (the role of the paper's per-Block kernel selection, Sec. 4.1). */
+typedef struct {
+  int32_t fused_exchange;  /* 1: the sweep writes the neighbours' ghost layers
+                              itself; 0: a separate copy kernel after the sweep */
+  int32_t item_cells;      /* target cells per work item (whole x-rows), >= 1 */
+  int32_t wg_size;         /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t persistent;      /* 0: one workgroup per item; k > 0: k workgroups per
+                              compute unit loop over the item list */
+  int32_t graph_steps;     /* time steps per captured HIP graph; 0: plain launches */
+  int32_t nontemporal;     /* 1: streaming (non-temporal) loads and stores */
+} lbm_schedule;
+
+typedef struct {
+  int64_t n_cells;          /* nx*ny*nz */
+  int64_t n_fluid;          /* cells that are not solid */
+  int32_t n_blocks;
+  int32_t n_items;          /* work items of the current schedule */
+  int64_t steps;            /* time steps since the last (re)initialisation */
+  int64_t device_bytes;     /* device memory held by the context */
+  double bytes_per_update;  /* algorithmic HBM bytes per fluid-cell update:
+                               19 loads + 19 stores of one stored value,
+                               plus the link mask when obstacles exist */
+  int32_t storage_bytes;    /* bytes per stored population */
+  int32_t has_obstacles;
+} lbm_info;
+
+/* Create a context for the Patch p->dims split into nblocks Blocks.
+ * The AABBs must tile the Patch exactly without overlap and form a
+ * Cartesian grid (every distinct lo/hi per axis is a cut shared by all Blocks
+ * it crosses); BlockID = index in `blocks`.  Block data live on the device;
+ * the management data (AABB, BlockID, neighbour table) is also kept on the
+ * host (Sec. 4.2).  State after creation: all fluid, rest equilibrium
+ * f~ = 0.  Errors: LBM_EINVAL (bad parameters or tiling), LBM_ENOMEM,
+ * LBM_EDEVICE.  *out is set only on success. */
+lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_t nblocks,
+                             lbm_ctx** out);
+
+/* Solid mask on the host, nx*ny*nz bytes, x fastest, nonzero = solid;
+ * NULL = all fluid.  Builds the per-cell link masks for half-way bounce-back
+ * at obstacles (Sec. 2.1) and resets the state to rest (f~ = 0). */
+lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid);
+
+/* Warm start: f~ = feq~(rho - rho0, u) of Eq. (2) in every fluid cell, 0 in
+ * solid cells.  Host arrays rho[N], u[3*N] (FP64).  Fills the ghost layers. */
+lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u);
+
+/* Enqueue n >= 0 time steps (each: stream-collide sweep over all Blocks plus
+ * the ghost exchange) on the context stream.  Asynchronous. */
+lbm_status lbm_step(lbm_ctx* c, int64_t n);
+
+/* Density and velocity used by the most recent collision (before any step:
+ * the initial field), FP64: rho[N], u[3*N]; solid cells give rho0 and 0.
+ * dst_is_device = 1: rho/u are device pointers.  Synchronises. */
+lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_device);
+
+/* r = ||u^n - u^(n-1)||_2 / ||u^n||_2 over fluid cells, FP64 (steady-state
+ * measure).  Needs >= 2 steps since the last (re)initialisation, else
+ * LBM_ESTATE.  Synchronises. */
+lbm_status lbm_residual(lbm_ctx* c, double* r);
+
+/* Global FP64 sums over fluid cells: mass = sum rho, mom = sum rho0 u. */
+lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]);
+
+/* Checkpoint: the current post-collision populations, 19 x N in [i][z][y][x],
+ * host buffer; as_fp64 = 1: FP64 values, 0: the storage type's raw values
+ * (8, 4 or 2 bytes each).  Solid cells read 0.  Synchronises. */
+lbm_status lbm_get_state(lbm_ctx* c, void* f, int32_t as_fp64);
+
+/* Restore a checkpoint of the same layout (solid entries are ignored and held
+ * at 0).  The state is taken as post-collision; the step counter is reset to
+ * 1 so that lbm_macroscopic reports its moments with the half-force shift. */
+lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64);
+
+lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s);
+/* Validate and apply a schedule (rebuilds the item list and drops captured
+ * graphs).  Results do not depend on the schedule, bit for bit. */
+lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s);
+
+/* Time candidate schedules for `trial_steps` steps each on this context and
+ * apply the fastest.  The state is saved before and restored after, so the
+ * simulation is unchanged.  cache_path (may be NULL) names a text file of
+ * earlier choices keyed by the problem signature; a hit skips the trials.
+ * The chosen schedule is written to *chosen when non-NULL. */
+lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
+                        lbm_schedule* chosen);
+
+/* Static facts and counters of a context.  Synchronises. */
+lbm_status lbm_info_get(lbm_ctx* c, lbm_info* info);
+
+lbm_status lbm_destroy(lbm_ctx* c);
+const char* lbm_strerror(lbm_status s);
+/* Text of the last error detected on this thread (empty if none). */
+const char* lbm_last_error(void);
+
+/* Device copy-bandwidth probe: copies `bytes` (a multiple of 16) from src to
+ * dst (device pointers) `reps` times on `stream` and returns the average
+ * time per copy in milliseconds -- the attainable-bandwidth benchmark of
+ * Sec. 3.1, written for gfx950. */
+lbm_status lbm_bw_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* stream,
+                        double* ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H_ */

@@ -1,0 +1,104 @@
+// lbm_internal.h -- data layout shared by the gfx950 kernels and the host runtime.
+//
+// Per Block (interior a x b x c cells, Sec. 4.2) and per grid (two grids, pull
+// scheme, Sec. 2.1) the populations are stored Structure-of-Arrays
+// (Sec. 3.2): 19 arrays f_i[z][y][x] that include a one-cell ghost layer in y
+// and z (rows y = -1, b and planes z = -1, c), with x-rows padded to a
+// multiple of 128 bytes so every row starts on a cache line.  The ghost layer
+// in x (x = -1 and x = a) lives in ten separate planes, five per side, holding
+// only the five populations that cross an x face (Sec. 4.4 counts 5 PDFs per
+// face cell); keeping it out of the rows keeps the interior aligned.
+//
+//   main:  base + i*Sf + (z+1)*Sz + (y+1)*Sx + x          0 <= x < a
+//   x-lo:  xg + k*P + (z+1)*Ry + (y+1)                    x = -1, k = klo(i)
+//   x-hi:  xg + (5+k)*P + (z+1)*Ry + (y+1)                x = a,  k = khi(i)
+//
+// Offsets are in elements of the storage type, relative to the grid pool.
+#pragma once
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kQ = 19;
+
+struct BlockDev {
+  int dim[3];       // a, b, c
+  int org[3];       // global cell of the Block's (0,0,0)
+  int Sx;           // x-row stride (elements)
+  int Ry;           // b + 2: rows per plane of an x-ghost plane
+  int P;            // x-ghost plane stride (elements)
+  int pad0;
+  long long Sz;     // Sx * (b + 2)
+  long long Sf;     // stride between the 19 population arrays
+  long long base;   // element offset of main[0][z=-1][y=-1][x=0]
+  long long xg;     // element offset of the 10 x-ghost planes
+  long long mask;   // offset of the Block's link masks (a*b*c words), -1: none
+  long long pad1;
+};
+
+// Neighbour entry of a Block for offset class d = 13 + dx + 3 dy + 9 dz:
+// id of the Block that owns the cells across that face/edge/corner (-1 beyond
+// a wall), and the translation from this Block's local coordinates to the
+// neighbour's (periodic images included).
+struct NbrDev {
+  int id, tx, ty, tz;
+};
+
+// Work item: x-rows [y0, y0 + nrows) of plane z of one Block.
+struct ItemDev {
+  int block, z, y0, nrows;
+};
+
+// Plain ghost-exchange task: ghost region of Block `dst` in offset class d,
+// one population direction i, region extent ext[3] starting at lo[3] (local
+// coordinates of dst, -1 or dim on the offset axes).
+struct XchgTask {
+  int dst, d, i, ncell;
+  int lo[3], ext[3];
+};
+
+// Link-mask word of a cell: bit i (1..18) set when x - e_i is a solid cell
+// (obstacle bounce-back link); bit 31 set when the cell itself is solid.
+constexpr uint32_t kSolidBit = 0x80000000u;
+
+struct GridGeom {
+  int n[3];         // global nx, ny, nz
+  int wall[3];      // 1: walls on both faces of the axis
+  int moving[6];    // face has a nonzero wall velocity
+};
+
+template <typename C>
+struct Phys {
+  C omega;          // 1/tau
+  C rho0;
+  C inv_rho0;
+  C fcoef;          // 1 - omega/2
+  C g[3];
+  C hg[3];          // g/2
+  C corr[kQ][6];    // 6 w_i rho0 (e_i . u_w[face])
+};
+
+struct SweepArgs {
+  const void* src;
+  void* dst;
+  const BlockDev* blocks;
+  const NbrDev* nbr;
+  const ItemDev* items;
+  const uint32_t* mask;
+  int nitems;
+  int pad;
+  GridGeom geo;
+};
+
+// Arguments of the per-cell utility kernels (init, macroscopic, reductions,
+// checkpoint, link masks): they walk the same item list as the sweep.
+struct CellArgs {
+  const BlockDev* blocks;
+  const ItemDev* items;
+  const uint32_t* mask;
+  int nitems;
+  int has_mask;
+  GridGeom geo;
+};
+
+}  // namespace lbm

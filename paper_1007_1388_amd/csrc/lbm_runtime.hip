@@ -1,0 +1,964 @@
+// lbm_runtime.hip -- host runtime behind include/lbm.h.
+//
+// Owns the Patch/Block management data (AABB, BlockID, neighbour table,
+// Sec. 4.2), the device field data of every Block, the work-item list that
+// the kernels walk, the captured HIP graphs of the time step and the
+// schedule autotuner (the per-Block kernel selection of Sec. 4.1, done by
+// measurement).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, const SweepArgs& a,
+                  const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
+void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
+                     int ntasks, int max_cells, hipStream_t s);
+void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
+void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const double* rho, const double* u,
+                    long long N, hipStream_t s);
+void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, const double hg[3], double* rho,
+                  double* u, long long N, hipStream_t s);
+void launch_reduce(int prec, const void* cur, const void* prev, const CellArgs& a, double rho0, const double hc[3],
+                   const double hp[3], int want_prev, double* partial, int nparts, double* out, hipStream_t s);
+void launch_get_state(int prec, bool f64, const void* grid, const CellArgs& a, void* out, long long N,
+                      hipStream_t s);
+void launch_set_state(int prec, bool f64, void* grid, const CellArgs& a, const void* in, long long N,
+                      hipStream_t s);
+void launch_copy16(const void* src, void* dst, long long n16, int grid, hipStream_t s);
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr int E3[kQ][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                           {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                           {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+double weight(int i) {
+  const int s = E3[i][0] * E3[i][0] + E3[i][1] * E3[i][1] + E3[i][2] * E3[i][2];
+  return s == 0 ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+int storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+
+long long roundup(long long v, long long m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  int prec = 1;
+  bool f64math = false;
+  int sbytes = 4;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  int cu_count = 256;
+
+  std::vector<lbm_aabb> aabb;
+  std::vector<BlockDev> bh;
+  std::vector<NbrDev> nbh;
+  std::vector<ItemDev> items_h;
+  std::vector<XchgTask> tasks_h;
+  int xchg_max_cells = 0;
+  GridGeom geo{};
+  Phys<double> phd{};
+  Phys<float> phf{};
+
+  // device memory
+  std::vector<std::pair<void*, size_t>> allocs;
+  size_t held = 0;
+  void* grid[2] = {nullptr, nullptr};
+  size_t grid_elems = 0;
+  BlockDev* d_blocks = nullptr;
+  NbrDev* d_nbr = nullptr;
+  ItemDev* d_items = nullptr;
+  size_t items_cap = 0;
+  XchgTask* d_tasks = nullptr;
+  uint32_t* d_mask = nullptr;
+  bool has_mask = false;
+  double* d_partial = nullptr;
+  int nparts = 1024;
+  double* d_red = nullptr;
+  void* d_stage = nullptr;
+  size_t stage_bytes = 0;
+
+  int cur = 0;
+  long long steps = 0;
+  long long n_cells = 0;
+  long long n_fluid = 0;
+  lbm_schedule sched{};
+
+  // captured graphs: [start parity] for 1 step and for graph_steps steps
+  hipGraphExec_t g_one[2] = {nullptr, nullptr};
+  hipGraphExec_t g_many[2] = {nullptr, nullptr};
+  bool graphs_ok = false;
+};
+
+namespace {
+
+void* dalloc(lbm_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* ptr = nullptr;
+  if (c->p.dev_alloc) {
+    ptr = c->p.dev_alloc(bytes, c->p.alloc_user);
+  } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    ptr = nullptr;
+  }
+  if (ptr) {
+    c->allocs.push_back({ptr, bytes});
+    c->held += bytes;
+  }
+  return ptr;
+}
+
+void dfree(lbm_ctx* c, void* ptr) {
+  if (!ptr) return;
+  for (size_t k = 0; k < c->allocs.size(); ++k) {
+    if (c->allocs[k].first == ptr) {
+      c->held -= c->allocs[k].second;
+      c->allocs.erase(c->allocs.begin() + k);
+      break;
+    }
+  }
+  if (c->p.dev_free) c->p.dev_free(ptr, c->p.alloc_user);
+  else (void)hipFree(ptr);
+}
+
+void drop_graphs(lbm_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->g_one[k]) (void)hipGraphExecDestroy(c->g_one[k]);
+    if (c->g_many[k]) (void)hipGraphExecDestroy(c->g_many[k]);
+    c->g_one[k] = c->g_many[k] = nullptr;
+  }
+  c->graphs_ok = false;
+}
+
+CellArgs cell_args(const lbm_ctx* c) {
+  CellArgs a;
+  a.blocks = c->d_blocks;
+  a.items = c->d_items;
+  a.mask = c->d_mask;
+  a.nitems = (int)c->items_h.size();
+  a.has_mask = c->has_mask ? 1 : 0;
+  a.geo = c->geo;
+  return a;
+}
+
+// Validate the Block AABBs: exact, non-overlapping tiling of the Patch that
+// forms a Cartesian grid.  Fills the per-axis cut lists and the
+// (ix, iy, iz) -> BlockID map.
+bool build_tiling(const int dims[3], const lbm_aabb* b, int n, std::vector<int> cuts[3], std::vector<int>& owner,
+                  std::string& err) {
+  for (int k = 0; k < 3; ++k) {
+    cuts[k].clear();
+    cuts[k].push_back(0);
+    cuts[k].push_back(dims[k]);
+  }
+  for (int j = 0; j < n; ++j) {
+    for (int k = 0; k < 3; ++k) {
+      if (b[j].lo[k] < 0 || b[j].hi[k] > dims[k] || b[j].lo[k] >= b[j].hi[k]) {
+        err = "block " + std::to_string(j) + ": empty or outside the domain";
+        return false;
+      }
+      cuts[k].push_back(b[j].lo[k]);
+      cuts[k].push_back(b[j].hi[k]);
+    }
+  }
+  long long ncell = 1;
+  for (int k = 0; k < 3; ++k) {
+    std::sort(cuts[k].begin(), cuts[k].end());
+    cuts[k].erase(std::unique(cuts[k].begin(), cuts[k].end()), cuts[k].end());
+    ncell *= (long long)(cuts[k].size() - 1);
+  }
+  if (ncell != n) {
+    err = "blocks do not form a Cartesian grid (" + std::to_string(n) + " blocks, " + std::to_string(ncell) +
+          " grid slots)";
+    return false;
+  }
+  const int nx = (int)cuts[0].size() - 1, ny = (int)cuts[1].size() - 1;
+  owner.assign((size_t)ncell, -1);
+  for (int j = 0; j < n; ++j) {
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = (int)(std::lower_bound(cuts[k].begin(), cuts[k].end(), b[j].lo[k]) - cuts[k].begin());
+      hi[k] = (int)(std::lower_bound(cuts[k].begin(), cuts[k].end(), b[j].hi[k]) - cuts[k].begin());
+      if (hi[k] != lo[k] + 1) {
+        err = "block " + std::to_string(j) + " spans more than one grid slot";
+        return false;
+      }
+    }
+    const size_t s = ((size_t)lo[2] * ny + lo[1]) * nx + lo[0];
+    if (owner[s] >= 0) {
+      err = "blocks " + std::to_string(owner[s]) + " and " + std::to_string(j) + " overlap";
+      return false;
+    }
+    owner[s] = j;
+  }
+  return true;
+}
+
+int slot_of(const std::vector<int>& cuts, int v) {
+  return (int)(std::upper_bound(cuts.begin(), cuts.end(), v) - cuts.begin()) - 1;
+}
+
+void build_items(lbm_ctx* c) {
+  c->items_h.clear();
+  const int target = std::max(1, c->sched.item_cells);
+  for (int j = 0; j < (int)c->bh.size(); ++j) {
+    const BlockDev& B = c->bh[j];
+    const int a = B.dim[0], b = B.dim[1], cz = B.dim[2];
+    const int rows = std::max(1, std::min(b, target / a));
+    for (int z = 0; z < cz; ++z)
+      for (int y = 0; y < b; y += rows) c->items_h.push_back({j, z, y, std::min(rows, b - y)});
+  }
+}
+
+lbm_status upload_items(lbm_ctx* c) {
+  const size_t need = c->items_h.size() * sizeof(ItemDev);
+  if (need > c->items_cap) {
+    if (c->d_items) dfree(c, c->d_items);
+    c->d_items = (ItemDev*)dalloc(c, need);
+    if (!c->d_items) return fail(LBM_ENOMEM, "item list allocation failed");
+    c->items_cap = need;
+  }
+  HIPCHK(hipMemcpy(c->d_items, c->items_h.data(), need, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+void build_tasks(lbm_ctx* c) {
+  c->tasks_h.clear();
+  c->xchg_max_cells = 0;
+  for (int j = 0; j < (int)c->bh.size(); ++j) {
+    const BlockDev& M = c->bh[j];
+    for (int d = 0; d < 27; ++d) {
+      if (d == 13 || c->nbh[(size_t)j * 27 + d].id < 0) continue;
+      const int off[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+      XchgTask t{};
+      t.dst = j;
+      t.d = d;
+      t.ncell = 1;
+      for (int k = 0; k < 3; ++k) {
+        t.lo[k] = off[k] < 0 ? -1 : (off[k] > 0 ? M.dim[k] : 0);
+        t.ext[k] = off[k] == 0 ? M.dim[k] : 1;
+        t.ncell *= t.ext[k];
+      }
+      for (int i = 1; i < kQ; ++i) {
+        bool ok = true, any = false;
+        for (int k = 0; k < 3; ++k) {
+          if (off[k] != 0) {
+            any = true;
+            if (E3[i][k] != -off[k]) ok = false;
+          }
+        }
+        if (ok && any) {
+          t.i = i;
+          c->tasks_h.push_back(t);
+          c->xchg_max_cells = std::max(c->xchg_max_cells, t.ncell);
+        }
+      }
+    }
+  }
+}
+
+// --- step launches -------------------------------------------------------
+SweepArgs sweep_args(const lbm_ctx* c, int from) {
+  SweepArgs a{};
+  a.src = c->grid[from];
+  a.dst = c->grid[1 - from];
+  a.blocks = c->d_blocks;
+  a.nbr = c->d_nbr;
+  a.items = c->d_items;
+  a.mask = c->d_mask;
+  a.nitems = (int)c->items_h.size();
+  a.geo = c->geo;
+  return a;
+}
+
+void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s) {
+  launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_tasks, (int)c->tasks_h.size(),
+                  c->xchg_max_cells, s);
+}
+
+void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
+  const SweepArgs a = sweep_args(c, from);
+  const int nitems = (int)c->items_h.size();
+  int grid = nitems;
+  if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
+  if (grid < 1) grid = 1;
+  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0, a,
+               c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+  if (!c->sched.fused_exchange) enqueue_exchange(c, 1 - from, s);
+}
+
+lbm_status capture(lbm_ctx* c, int from, int nsteps, hipGraphExec_t* out) {
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  int g = from;
+  for (int k = 0; k < nsteps; ++k) {
+    enqueue_step(c, g, c->cap_stream);
+    g = 1 - g;
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamEndCapture(c->cap_stream, &graph));
+  hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+lbm_status ensure_graphs(lbm_ctx* c) {
+  if (c->graphs_ok || c->sched.graph_steps <= 0) return LBM_OK;
+  drop_graphs(c);
+  for (int from = 0; from < 2; ++from) {
+    lbm_status s = capture(c, from, 1, &c->g_one[from]);
+    if (s != LBM_OK) return s;
+    s = capture(c, from, c->sched.graph_steps, &c->g_many[from]);
+    if (s != LBM_OK) return s;
+  }
+  c->graphs_ok = true;
+  return LBM_OK;
+}
+
+lbm_status run_steps(lbm_ctx* c, long long n) {
+  if (n <= 0) return LBM_OK;
+  if (c->sched.graph_steps > 0) {
+    lbm_status s = ensure_graphs(c);
+    if (s != LBM_OK) return s;
+    const long long G = c->sched.graph_steps;
+    while (n >= G) {
+      HIPCHK(hipGraphLaunch(c->g_many[c->cur], c->stream));
+      if (G & 1) c->cur = 1 - c->cur;
+      n -= G;
+      c->steps += G;
+    }
+    while (n > 0) {
+      HIPCHK(hipGraphLaunch(c->g_one[c->cur], c->stream));
+      c->cur = 1 - c->cur;
+      --n;
+      c->steps += 1;
+    }
+    return LBM_OK;
+  }
+  for (long long k = 0; k < n; ++k) {
+    enqueue_step(c, c->cur, c->stream);
+    c->cur = 1 - c->cur;
+    c->steps += 1;
+  }
+  HIPCHK(hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status ensure_stage(lbm_ctx* c, size_t bytes) {
+  if (bytes <= c->stage_bytes) return LBM_OK;
+  if (c->d_stage) dfree(c, c->d_stage);
+  c->d_stage = dalloc(c, bytes);
+  if (!c->d_stage) {
+    c->stage_bytes = 0;
+    return fail(LBM_ENOMEM, "staging buffer allocation failed");
+  }
+  c->stage_bytes = bytes;
+  return LBM_OK;
+}
+
+// g/2 correction of a grid: post-collision states carry rho0 g extra momentum.
+void half_force(const lbm_ctx* c, bool post, double hg[3]) {
+  for (int k = 0; k < 3; ++k) hg[k] = post ? 0.5 * c->p.force[k] : 0.0;
+}
+
+lbm_status reduce(lbm_ctx* c, bool want_prev, double out[6]) {
+  double hc[3], hp[3];
+  half_force(c, c->steps >= 1, hc);
+  half_force(c, c->steps >= 2, hp);
+  const CellArgs a = cell_args(c);
+  const int nparts = std::max(1, std::min(c->nparts, a.nitems));
+  launch_reduce(c->prec, c->grid[c->cur], c->grid[1 - c->cur], a, c->p.rho0, hc, hp, want_prev ? 1 : 0,
+                c->d_partial, nparts, c->d_red, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, c->d_red, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(out[k])) return fail(LBM_EUNSTABLE, "non-finite global sum");
+  return LBM_OK;
+}
+
+lbm_status zero_grids(lbm_ctx* c) {
+  for (int g = 0; g < 2; ++g)
+    HIPCHK(hipMemsetAsync(c->grid[g], 0, c->grid_elems * c->sbytes, c->stream));
+  return LBM_OK;
+}
+
+std::string sched_str(const lbm_schedule& s) {
+  std::ostringstream o;
+  o << s.fused_exchange << " " << s.item_cells << " " << s.wg_size << " " << s.persistent << " " << s.graph_steps
+    << " " << s.nontemporal;
+  return o.str();
+}
+
+bool sched_valid(const lbm_schedule& s, std::string& err) {
+  const int wg = s.wg_size;
+  if (!(wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024)) {
+    err = "wg_size must be 64, 128, 256, 512 or 1024";
+    return false;
+  }
+  if (s.item_cells < 1 || s.item_cells > (1 << 22)) {
+    err = "item_cells out of range";
+    return false;
+  }
+  if (s.persistent < 0 || s.persistent > 64 || s.graph_steps < 0 || s.graph_steps > 4096) {
+    err = "persistent or graph_steps out of range";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char* lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "device error";
+    case LBM_ESTATE: return "invalid state";
+    case LBM_EUNSTABLE: return "simulation became unstable (non-finite values)";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  drop_graphs(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return LBM_OK;
+}
+
+lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_t nblocks, lbm_ctx** out) {
+  g_last_error.clear();
+  if (!p || !blocks || !out || nblocks <= 0) return fail(LBM_EINVAL, "NULL argument or no blocks");
+  for (int k = 0; k < 3; ++k)
+    if (p->dims[k] < 1) return fail(LBM_EINVAL, "dims must be >= 1");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+  if (p->precision < LBM_F64 || p->precision > LBM_BF16S) return fail(LBM_EINVAL, "bad precision");
+  for (int k = 0; k < 3; ++k) {
+    if (!std::isfinite(p->force[k])) return fail(LBM_EINVAL, "force must be finite");
+    const int f0 = p->face[2 * k], f1 = p->face[2 * k + 1];
+    if ((f0 != LBM_PERIODIC && f0 != LBM_WALL) || f0 != f1)
+      return fail(LBM_EINVAL, "opposite faces must both be PERIODIC or both WALL");
+  }
+  for (int f = 0; f < 6; ++f) {
+    const int axis = f / 2;
+    for (int k = 0; k < 3; ++k) {
+      const double v = p->wall_u[f][k];
+      if (!std::isfinite(v)) return fail(LBM_EINVAL, "wall velocity must be finite");
+      if (v != 0.0 && (k == axis || p->face[f] == LBM_PERIODIC))
+        return fail(LBM_EINVAL, "wall velocity must be tangential and only on WALL faces");
+    }
+  }
+  std::vector<int> cuts[3], owner;
+  std::string err;
+  if (!build_tiling(p->dims, blocks, nblocks, cuts, owner, err)) return fail(LBM_EINVAL, err);
+
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->prec = p->precision;
+  c->f64math = (p->precision == LBM_F64) || (p->precision == LBM_F32 && p->fp64_math);
+  c->sbytes = storage_bytes(c->prec);
+  c->stream = (hipStream_t)p->stream;
+  c->aabb.assign(blocks, blocks + nblocks);
+  c->n_cells = (long long)p->dims[0] * p->dims[1] * p->dims[2];
+  c->n_fluid = c->n_cells;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(LBM_EDEVICE, "no HIP device");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->cu_count = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(LBM_EDEVICE, "stream creation failed");
+  }
+
+  // geometry and physics constants
+  for (int k = 0; k < 3; ++k) {
+    c->geo.n[k] = p->dims[k];
+    c->geo.wall[k] = p->face[2 * k] == LBM_WALL ? 1 : 0;
+  }
+  for (int f = 0; f < 6; ++f)
+    c->geo.moving[f] = (p->wall_u[f][0] != 0.0 || p->wall_u[f][1] != 0.0 || p->wall_u[f][2] != 0.0) ? 1 : 0;
+  const double omega = 1.0 / p->tau;
+  c->phd.omega = omega;
+  c->phd.rho0 = p->rho0;
+  c->phd.inv_rho0 = 1.0 / p->rho0;
+  c->phd.fcoef = 1.0 - 0.5 * omega;
+  for (int k = 0; k < 3; ++k) {
+    c->phd.g[k] = p->force[k];
+    c->phd.hg[k] = 0.5 * p->force[k];
+  }
+  for (int i = 0; i < kQ; ++i)
+    for (int f = 0; f < 6; ++f) {
+      const double eu = E3[i][0] * p->wall_u[f][0] + E3[i][1] * p->wall_u[f][1] + E3[i][2] * p->wall_u[f][2];
+      c->phd.corr[i][f] = 6.0 * weight(i) * p->rho0 * eu;
+    }
+  c->phf.omega = (float)c->phd.omega;
+  c->phf.rho0 = (float)c->phd.rho0;
+  c->phf.inv_rho0 = (float)c->phd.inv_rho0;
+  c->phf.fcoef = (float)c->phd.fcoef;
+  for (int k = 0; k < 3; ++k) {
+    c->phf.g[k] = (float)c->phd.g[k];
+    c->phf.hg[k] = (float)c->phd.hg[k];
+  }
+  for (int i = 0; i < kQ; ++i)
+    for (int f = 0; f < 6; ++f) c->phf.corr[i][f] = (float)c->phd.corr[i][f];
+
+  // per-Block layout (see lbm_internal.h)
+  const long long align = 128 / c->sbytes;  // elements per 128-byte line
+  long long off = 0;
+  c->bh.resize(nblocks);
+  for (int j = 0; j < nblocks; ++j) {
+    BlockDev& B = c->bh[j];
+    std::memset(&B, 0, sizeof(B));
+    for (int k = 0; k < 3; ++k) {
+      B.org[k] = blocks[j].lo[k];
+      B.dim[k] = blocks[j].hi[k] - blocks[j].lo[k];
+    }
+    B.Sx = (int)roundup(B.dim[0], align);
+    B.Ry = B.dim[1] + 2;
+    B.Sz = (long long)B.Sx * (B.dim[1] + 2);
+    const long long fmin = B.Sz * (B.dim[2] + 2);
+    // stagger the 19 streams so they do not start on the same HBM channel
+    B.Sf = roundup(fmin, 4096 / c->sbytes) + 768 / c->sbytes;
+    B.P = (int)roundup((long long)(B.dim[1] + 2) * (B.dim[2] + 2), 256 / c->sbytes);
+    B.base = off;
+    B.xg = off + (long long)kQ * B.Sf;
+    off = roundup(B.xg + 10LL * B.P, 4096 / c->sbytes);
+    B.mask = -1;
+  }
+  c->grid_elems = (size_t)off;
+
+  // neighbour table: Block across each face/edge/corner, with translation
+  c->nbh.assign((size_t)nblocks * 27, NbrDev{-1, 0, 0, 0});
+  const int gsz[3] = {(int)cuts[0].size() - 1, (int)cuts[1].size() - 1, (int)cuts[2].size() - 1};
+  for (int j = 0; j < nblocks; ++j) {
+    for (int d = 0; d < 27; ++d) {
+      if (d == 13) continue;
+      const int off3[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+      int rep[3], q[3];
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        rep[k] = off3[k] < 0 ? blocks[j].lo[k] : (off3[k] > 0 ? blocks[j].hi[k] - 1 : blocks[j].lo[k]);
+        q[k] = rep[k] + off3[k];
+        if (q[k] < 0 || q[k] >= p->dims[k]) {
+          if (c->geo.wall[k]) ok = false;
+          else q[k] = (q[k] + p->dims[k]) % p->dims[k];
+        }
+      }
+      if (!ok) continue;
+      const int s0 = slot_of(cuts[0], q[0]), s1 = slot_of(cuts[1], q[1]), s2 = slot_of(cuts[2], q[2]);
+      const int m = owner[((size_t)s2 * gsz[1] + s1) * gsz[0] + s0];
+      NbrDev& nb = c->nbh[(size_t)j * 27 + d];
+      nb.id = m;
+      // rep in m's frame is q - org_m - off; in j's frame it is rep - org_j
+      nb.tx = (q[0] - blocks[m].lo[0] - off3[0]) - (rep[0] - blocks[j].lo[0]);
+      nb.ty = (q[1] - blocks[m].lo[1] - off3[1]) - (rep[1] - blocks[j].lo[1]);
+      nb.tz = (q[2] - blocks[m].lo[2] - off3[2]) - (rep[2] - blocks[j].lo[2]);
+    }
+  }
+
+  c->sched.fused_exchange = 1;
+  c->sched.item_cells = 512;
+  c->sched.wg_size = 256;
+  c->sched.persistent = 0;
+  c->sched.graph_steps = 0;
+  c->sched.nontemporal = 1;
+  build_items(c);
+  build_tasks(c);
+
+  auto bail = [&](lbm_status s, const char* msg) {
+    lbm_destroy(c);
+    return fail(s, msg);
+  };
+  const size_t gbytes = c->grid_elems * c->sbytes;
+  c->grid[0] = dalloc(c, gbytes);
+  c->grid[1] = dalloc(c, gbytes);
+  c->d_blocks = (BlockDev*)dalloc(c, sizeof(BlockDev) * nblocks);
+  c->d_nbr = (NbrDev*)dalloc(c, sizeof(NbrDev) * c->nbh.size());
+  c->d_tasks = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->tasks_h.size()));
+  c->d_partial = (double*)dalloc(c, sizeof(double) * 6 * c->nparts);
+  c->d_red = (double*)dalloc(c, sizeof(double) * 8);
+  if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_tasks || !c->d_partial || !c->d_red)
+    return bail(LBM_ENOMEM, "device allocation failed");
+  if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!c->tasks_h.empty() && hipMemcpy(c->d_tasks, c->tasks_h.data(), sizeof(XchgTask) * c->tasks_h.size(),
+                                        hipMemcpyHostToDevice) != hipSuccess))
+    return bail(LBM_EDEVICE, "upload of block tables failed");
+  if (upload_items(c) != LBM_OK) return bail(LBM_ENOMEM, "item list upload failed");
+  if (zero_grids(c) != LBM_OK || hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(LBM_EDEVICE, "grid initialisation failed");
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  drop_graphs(c);
+  bool any = false;
+  long long nsolid = 0;
+  if (solid) {
+    for (long long k = 0; k < c->n_cells; ++k)
+      if (solid[k]) ++nsolid;
+    any = nsolid > 0;
+  }
+  if (any) {
+    if (!c->d_mask) {
+      long long moff = 0;
+      for (auto& B : c->bh) {
+        B.mask = moff;
+        moff += (long long)B.dim[0] * B.dim[1] * B.dim[2];
+      }
+      c->d_mask = (uint32_t*)dalloc(c, sizeof(uint32_t) * moff);
+      if (!c->d_mask) {
+        for (auto& B : c->bh) B.mask = -1;
+        return fail(LBM_ENOMEM, "link-mask allocation failed");
+      }
+      HIPCHK(hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * c->bh.size(), hipMemcpyHostToDevice));
+    }
+    lbm_status s = ensure_stage(c, (size_t)c->n_cells);
+    if (s != LBM_OK) return s;
+    HIPCHK(hipMemcpyAsync(c->d_stage, solid, (size_t)c->n_cells, hipMemcpyHostToDevice, c->stream));
+    c->has_mask = true;
+    CellArgs a = cell_args(c);
+    a.has_mask = 0;
+    launch_linkmask((const uint8_t*)c->d_stage, a, c->d_mask, c->stream);
+    HIPCHK(hipGetLastError());
+  } else {
+    c->has_mask = false;
+  }
+  c->n_fluid = c->n_cells - nsolid;
+  lbm_status s = zero_grids(c);
+  if (s != LBM_OK) return s;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
+  if (!c || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  const size_t N = (size_t)c->n_cells;
+  lbm_status s = ensure_stage(c, 4 * N * sizeof(double));
+  if (s != LBM_OK) return s;
+  double* d = (double*)c->d_stage;
+  HIPCHK(hipMemcpyAsync(d, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + N, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_init_eq(c->prec, c->grid[c->cur], cell_args(c), c->p.rho0, d, d + N, (long long)N, c->stream);
+  enqueue_exchange(c, c->cur, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->steps = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  return run_steps(c, n);
+}
+
+lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_device) {
+  if (!c || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  const size_t N = (size_t)c->n_cells;
+  double hg[3];
+  half_force(c, c->steps >= 1, hg);
+  double *dr = rho, *du = u;
+  if (!dst_is_device) {
+    lbm_status s = ensure_stage(c, 4 * N * sizeof(double));
+    if (s != LBM_OK) return s;
+    dr = (double*)c->d_stage;
+    du = dr + N;
+  }
+  launch_macro(c->prec, c->grid[c->cur], cell_args(c), c->p.rho0, hg, dr, du, (long long)N, c->stream);
+  HIPCHK(hipGetLastError());
+  if (!dst_is_device) {
+    HIPCHK(hipMemcpyAsync(rho, dr, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(u, du, 3 * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_residual(lbm_ctx* c, double* r) {
+  if (!c || !r) return fail(LBM_EINVAL, "NULL argument");
+  if (c->steps < 2) return fail(LBM_ESTATE, "residual needs >= 2 steps since initialisation");
+  double s[6];
+  lbm_status st = reduce(c, true, s);
+  if (st != LBM_OK) return st;
+  *r = std::sqrt(s[4]) / std::sqrt(s[5]);
+  if (!std::isfinite(*r)) *r = s[4] == 0.0 ? 0.0 : INFINITY;
+  return LBM_OK;
+}
+
+lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]) {
+  if (!c || !mass || !mom) return fail(LBM_EINVAL, "NULL argument");
+  double s[6];
+  lbm_status st = reduce(c, false, s);
+  if (st != LBM_OK) return st;
+  *mass = (double)c->n_fluid * c->p.rho0 + s[0];
+  mom[0] = s[1];
+  mom[1] = s[2];
+  mom[2] = s[3];
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* f, int32_t as_fp64) {
+  if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t N = (size_t)c->n_cells;
+  const size_t bytes = (size_t)kQ * N * (as_fp64 ? sizeof(double) : c->sbytes);
+  lbm_status s = ensure_stage(c, bytes);
+  if (s != LBM_OK) return s;
+  launch_get_state(c->prec, as_fp64 != 0, c->grid[c->cur], cell_args(c), c->d_stage, (long long)N, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(f, c->d_stage, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64) {
+  if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t N = (size_t)c->n_cells;
+  const size_t bytes = (size_t)kQ * N * (as_fp64 ? sizeof(double) : c->sbytes);
+  lbm_status s = ensure_stage(c, bytes);
+  if (s != LBM_OK) return s;
+  HIPCHK(hipMemcpyAsync(c->d_stage, f, bytes, hipMemcpyHostToDevice, c->stream));
+  launch_set_state(c->prec, as_fp64 != 0, c->grid[c->cur], cell_args(c), c->d_stage, (long long)N, c->stream);
+  enqueue_exchange(c, c->cur, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->steps = 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s) {
+  if (!c || !s) return fail(LBM_EINVAL, "NULL argument");
+  *s = c->sched;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s) {
+  if (!c || !s) return fail(LBM_EINVAL, "NULL argument");
+  std::string err;
+  if (!sched_valid(*s, err)) return fail(LBM_EINVAL, err);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  const lbm_schedule old = c->sched;
+  c->sched = *s;
+  build_items(c);
+  lbm_status st = upload_items(c);
+  if (st != LBM_OK) {
+    c->sched = old;
+    build_items(c);
+    (void)upload_items(c);
+    return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_info_get(lbm_ctx* c, lbm_info* info) {
+  if (!c || !info) return fail(LBM_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  info->n_cells = c->n_cells;
+  info->n_fluid = c->n_fluid;
+  info->n_blocks = (int32_t)c->bh.size();
+  info->n_items = (int32_t)c->items_h.size();
+  info->steps = c->steps;
+  info->device_bytes = (int64_t)c->held;
+  info->storage_bytes = c->sbytes;
+  info->has_obstacles = c->has_mask ? 1 : 0;
+  info->bytes_per_update = 2.0 * kQ * c->sbytes;
+  if (c->has_mask) info->bytes_per_update += 4.0 * (double)c->n_cells / (double)std::max(1LL, c->n_fluid);
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps, lbm_schedule* chosen) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (trial_steps < 1) trial_steps = 10;
+  // problem signature
+  std::ostringstream key;
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, c->device));
+  key << prop.gcnArchName << "|p" << c->prec << "m" << c->f64math << "o" << c->has_mask << "|" << c->p.dims[0]
+      << "x" << c->p.dims[1] << "x" << c->p.dims[2] << "|nb" << c->bh.size();
+  {
+    unsigned long long h = 1469598103934665603ULL;
+    for (const auto& b : c->aabb)
+      for (int k = 0; k < 3; ++k) {
+        h = (h ^ (unsigned long long)b.lo[k]) * 1099511628211ULL;
+        h = (h ^ (unsigned long long)b.hi[k]) * 1099511628211ULL;
+      }
+    key << "|h" << std::hex << h;
+  }
+  const std::string k = key.str();
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string kk;
+      lbm_schedule s{};
+      if (ls >> kk >> s.fused_exchange >> s.item_cells >> s.wg_size >> s.persistent >> s.graph_steps >>
+          s.nontemporal) {
+        std::string err;
+        if (kk == k && sched_valid(s, err)) {
+          lbm_status st = lbm_set_schedule(c, &s);
+          if (st == LBM_OK && chosen) *chosen = s;
+          return st;
+        }
+      }
+    }
+  }
+  // save both grids; the trials advance a copy of the simulation
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const size_t gbytes = c->grid_elems * c->sbytes;
+  void* save = dalloc(c, 2 * gbytes);
+  if (!save) return fail(LBM_ENOMEM, "autotune backup allocation failed");
+  HIPCHK(hipMemcpyAsync(save, c->grid[0], gbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync((char*)save + gbytes, c->grid[1], gbytes, hipMemcpyDeviceToDevice, c->stream));
+  const int cur0 = c->cur;
+  const long long steps0 = c->steps;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto timeit = [&](const lbm_schedule& s, double* ms) -> lbm_status {
+    lbm_status st = lbm_set_schedule(c, &s);
+    if (st != LBM_OK) return st;
+    st = run_steps(c, 2);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipEventRecord(e0, c->stream));
+    st = run_steps(c, trial_steps);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / trial_steps;
+    return LBM_OK;
+  };
+  lbm_schedule best = c->sched;
+  double best_ms = 1e30;
+  lbm_status st = timeit(best, &best_ms);
+  // coordinate descent over the schedule knobs
+  const std::vector<int> cells = {128, 256, 512, 1024, 2048, 4096};
+  const std::vector<int> wgs = {128, 256, 512, 1024};
+  const std::vector<int> pers = {0, 2, 4, 8, 16};
+  for (int pass = 0; pass < 2 && st == LBM_OK; ++pass) {
+    for (int knob = 0; knob < 5 && st == LBM_OK; ++knob) {
+      std::vector<lbm_schedule> cand;
+      for (size_t q = 0; q < (knob == 0 ? cells.size() : knob == 1 ? wgs.size() : knob == 2 ? pers.size() : 2);
+           ++q) {
+        lbm_schedule s = best;
+        if (knob == 0) s.item_cells = cells[q];
+        if (knob == 1) s.wg_size = wgs[q];
+        if (knob == 2) s.persistent = pers[q];
+        if (knob == 3) s.nontemporal = (int)q;
+        if (knob == 4) s.fused_exchange = (int)q;
+        cand.push_back(s);
+      }
+      for (const auto& s : cand) {
+        double ms = 0;
+        st = timeit(s, &ms);
+        if (st != LBM_OK) break;
+        if (ms < best_ms * 0.995) {
+          best_ms = ms;
+          best = s;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore the simulation
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipMemcpyAsync(c->grid[0], save, gbytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(c->grid[1], (char*)save + gbytes, gbytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  dfree(c, save);
+  c->cur = cur0;
+  c->steps = steps0;
+  if (st != LBM_OK) return st;
+  best.graph_steps = c->sched.graph_steps;
+  st = lbm_set_schedule(c, &best);
+  if (st != LBM_OK) return st;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    if (o) o << k << " " << sched_str(best) << "\n";
+  }
+  if (chosen) *chosen = best;
+  return LBM_OK;
+}
+
+lbm_status lbm_bw_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* stream, double* ms) {
+  if (!dst || !src || !ms || bytes == 0 || (bytes % 16) != 0 || reps < 1)
+    return fail(LBM_EINVAL, "bad probe arguments");
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, cus = 256;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  const long long n16 = (long long)(bytes / 16);
+  const int grid = (int)std::min<long long>((n16 + 255) / 256, (long long)cus * 16);
+  launch_copy16(src, dst, n16, grid, s);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) launch_copy16(src, dst, n16, grid, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return LBM_OK;
+}
+
+}  // extern "C"

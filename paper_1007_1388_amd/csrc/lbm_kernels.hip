@@ -14,6 +14,11 @@
 
 #include "lbm_internal.h"
 
+// No implicit multiply-add contraction: every instantiation of a kernel must
+// round exactly alike (schedules, exchange variants and Block tilings are
+// bit-identical), so fused multiply-adds are written out where wanted.
+#pragma clang fp contract(off)
+
 namespace lbm {
 
 // ------------------------------------------------------------------ lattice
@@ -169,11 +174,11 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs& A, const Phys<C>& ph
     if (EZd(i) > 0) jz += f[i];
     if (EZd(i) < 0) jz -= f[i];
   }
-  const C ux = jx * ph.inv_rho0 + ph.hg[0];
-  const C uy = jy * ph.inv_rho0 + ph.hg[1];
-  const C uz = jz * ph.inv_rho0 + ph.hg[2];
-  const C uu15 = (C)1.5 * (ux * ux + uy * uy + uz * uz);
-  const C ug = ux * ph.g[0] + uy * ph.g[1] + uz * ph.g[2];
+  const C ux = fma(jx, ph.inv_rho0, ph.hg[0]);
+  const C uy = fma(jy, ph.inv_rho0, ph.hg[1]);
+  const C uz = fma(jz, ph.inv_rho0, ph.hg[2]);
+  const C uu15 = (C)1.5 * fma(ux, ux, fma(uy, uy, uz * uz));
+  const C ug = fma(ux, ph.g[0], fma(uy, ph.g[1], uz * ph.g[2]));
 
   const bool edge = FUSED && ((x == 0) | (x == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
 #pragma unroll
@@ -187,9 +192,10 @@ __device__ __forceinline__ void sweep_cell(const SweepArgs& A, const Phys<C>& ph
     if (ey < 0) { eu -= uy; eg -= ph.g[1]; }
     if (ez > 0) { eu += uz; eg += ph.g[2]; }
     if (ez < 0) { eu -= uz; eg -= ph.g[2]; }
-    const C feq = w * (drho + ph.rho0 * ((C)3 * eu + (C)4.5 * eu * eu - uu15));
-    const C F = w * ph.rho0 * ((C)3 * (eg - ug) + (C)9 * eu * eg);
-    const C post = f[i] - ph.omega * (f[i] - feq) + ph.fcoef * F;
+    // feq~ = w [drho + rho0 (3 eu + 4.5 eu^2 - 1.5 u.u)],  F = w rho0 [3 (eg - ug) + 9 eu eg]
+    const C feq = w * fma(ph.rho0, fma((C)4.5 * eu, eu, (C)3 * eu - uu15), drho);
+    const C F = (w * ph.rho0) * fma((C)9 * eu, eg, (C)3 * (eg - ug));
+    const C post = fma(ph.fcoef, F, fma(-ph.omega, f[i] - feq, f[i]));
     const T out = from_c<PREC, C>(post);
     st<T, NT>(dst + cell + (long long)i * B.Sf, out);
     if (FUSED && i > 0 && edge) {

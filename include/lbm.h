@@ -89,7 +89,7 @@ typedef struct {
   int32_t fused_exchange;  /* 1: the sweep writes the neighbours' ghost layers
                               itself; 0: a separate copy kernel after the sweep */
   int32_t item_cells;      /* target cells per work item (whole x-rows), >= 1 */
-  int32_t wg_size;         /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t wg_size;         /* threads per workgroup: 64, 128 or 256 */
   int32_t persistent;      /* 0: one workgroup per item; k > 0: k workgroups per
                               compute unit loop over the item list */
   int32_t graph_steps;     /* time steps per captured HIP graph; 0: plain launches */

@@ -67,14 +67,35 @@ struct GridGeom {
   int moving[6];    // face has a nonzero wall velocity
 };
 
+// Where a Block's boundary value of direction i goes when the fused
+// exchange writes it into the ghost layer of neighbour M (one entry per
+// Block and offset class d):
+//   kind 1 (M's main arrays):   main0 + i*Sf + z*Sz + y*Sx + x
+//   kind 2 (M's x-ghost planes): xg0 + k*P + z*Ry + y,  k = slot of i
+// with (x, y, z) the sender's local cell; the translation into M's frame and
+// the plane side are folded into main0 / xg0.  kind 0: no neighbour (wall).
+struct GhostTgt {
+  long long main0;
+  long long xg0;
+  long long Sz;
+  long long Sf;
+  int Sx, Ry, P, kind;
+};
+
 template <typename C>
 struct Phys {
   C omega;          // 1/tau
+  C omc;            // 1 - 1/tau
   C rho0;
   C inv_rho0;
   C fcoef;          // 1 - omega/2
+  C rho0x3;         // 3 rho0
   C g[3];
   C hg[3];          // g/2
+  C w[kQ];          // lattice weights
+  C c3w[kQ];        // 3 w_i rho0
+  C c9g[kQ];        // 9 w_i rho0 (e_i . g)
+  C cfa[kQ];        // (1 - omega/2) 3 w_i rho0 (e_i . g)
   C corr[kQ][6];    // 6 w_i rho0 (e_i . u_w[face])
 };
 
@@ -85,6 +106,7 @@ struct SweepArgs {
   const NbrDev* nbr;
   const ItemDev* items;
   const uint32_t* mask;
+  const GhostTgt* ghost;  // [block][27]
   int nitems;
   int pad;
   GridGeom geo;

@@ -104,135 +104,342 @@ __device__ __forceinline__ long long main_off(const BlockDev& B, int i, int x, i
 }
 
 // ------------------------------------------------------------------- sweep
-// One fluid cell: pull (Sec. 2.1, pull scheme), half-way bounce-back with
-// wall velocity (Sec. 2.1, bounce-back rule), moments, BGK collision with the
-// shifted incompressible equilibrium of Eq. (2) and the Guo force term,
-// aligned store; with FUSED also the ghost-layer copy of the values that the
-// neighbouring Blocks pull in the next step (Sec. 4.4 on-GPU copies, fused).
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT>
-__device__ __forceinline__ void sweep_cell(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B,
-                                           int bid, int x, int y, int z) {
+template <int BYTES> struct Raw;
+template <> struct Raw<2> { typedef uint16_t V; };
+template <> struct Raw<4> { typedef uint32_t V; };
+template <> struct Raw<8> { typedef uint32_t V __attribute__((ext_vector_type(2))); };
+template <> struct Raw<16> { typedef uint32_t V __attribute__((ext_vector_type(4))); };
+
+// One value at a scalar base plus a 32-bit lane byte offset (a single
+// global instruction with the base in SGPRs).
+template <typename T, bool NT>
+__device__ __forceinline__ T ldo(const T* base, uint32_t boff) {
+  return ld<T, NT>((const T*)((const char*)base + boff));
+}
+
+// VEC consecutive values at a scalar base plus a 32-bit lane byte offset.
+template <typename T, int VEC, bool NT>
+__device__ __forceinline__ void vld(const T* base, uint32_t boff, T (&out)[VEC]) {
+  typedef typename Raw<sizeof(T) * VEC>::V V;
+  const V v = ld<V, NT>((const V*)((const char*)base + boff));
+  __builtin_memcpy(out, &v, sizeof(V));
+}
+template <typename T, int VEC, bool NT>
+__device__ __forceinline__ void vst(T* base, uint32_t boff, const T (&in)[VEC]) {
+  typedef typename Raw<sizeof(T) * VEC>::V V;
+  V v;
+  __builtin_memcpy(&v, in, sizeof(V));
+  st<V, NT>((V*)((char*)base + boff), v);
+}
+template <typename T>
+__device__ __forceinline__ T sh_up(T v) {  // value of lane - 1
+  if constexpr (sizeof(T) == 2) return (T)__shfl_up((int)v, 1, 64);
+  else return __shfl_up(v, 1, 64);
+}
+template <typename T>
+__device__ __forceinline__ T sh_down(T v) {  // value of lane + 1
+  if constexpr (sizeof(T) == 2) return (T)__shfl_down((int)v, 1, 64);
+  else return __shfl_down(v, 1, 64);
+}
+
+template <typename A_, typename B_> constexpr bool kSameType = false;
+template <typename A_> constexpr bool kSameType<A_, A_> = true;
+
+// Flags of the wall faces that the sources of a lane's cells lie beyond.
+struct WallFlags {
+  bool lox, hix, loy, hiy, loz, hiz;
+};
+
+// Wall link of direction i at element k of VEC: the source lies beyond a
+// wall face (x faces only concern the first / last element of the lane).
+template <int VEC>
+__device__ __forceinline__ bool wall_link(const WallFlags& w, int i, int k) {
+  const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
+  bool b = false;
+  if (ex > 0 && k == 0) b = b || w.lox;
+  if (ex < 0 && k == VEC - 1) b = b || w.hix;
+  if (ey > 0) b = b || w.loy;
+  if (ey < 0) b = b || w.hiy;
+  if (ez > 0) b = b || w.loz;
+  if (ez < 0) b = b || w.hiz;
+  return b;
+}
+
+// 6 w_i rho0 (e_i . u_w) of the first moving face (order -x,+x,-y,+y,-z,+z)
+// that the source of a wall link lies beyond.
+template <typename C, int VEC>
+__device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, const WallFlags& w, int i, int k) {
+  const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
+  C cw = (C)0;
+  if (ez > 0 && w.loz && A.geo.moving[4]) cw = ph.corr[i][4];
+  if (ez < 0 && w.hiz && A.geo.moving[5]) cw = ph.corr[i][5];
+  if (ey > 0 && w.loy && A.geo.moving[2]) cw = ph.corr[i][2];
+  if (ey < 0 && w.hiy && A.geo.moving[3]) cw = ph.corr[i][3];
+  if (ex > 0 && k == 0 && w.lox && A.geo.moving[0]) cw = ph.corr[i][0];
+  if (ex < 0 && k == VEC - 1 && w.hix && A.geo.moving[1]) cw = ph.corr[i][1];
+  return cw;
+}
+
+// One wave updates a row segment: each lane owns VEC consecutive cells of a
+// row, xw lanes per row (the smallest power of two covering the row, at most
+// 64), 64/xw rows per wave, so the plane z and the first row y0w are uniform
+// and every stream is one aligned vector access at a scalar base plus the
+// lane's offset.  The x +- 1 neighbours come from the adjacent lane (lane
+// shuffle), from the next row segment, or from the x-ghost planes.  Per cell:
+// pull (Sec. 2.1, pull scheme); half-way bounce-back with wall velocity
+// (Sec. 2.1, bounce-back rule); moments; BGK collision with the shifted
+// incompressible equilibrium of Eq. (2) and the Guo force term, evaluated per
+// pair of opposite directions (the even part of feq and F is shared, the odd
+// part flips sign); aligned stores; with FUSED also the copy of boundary
+// values into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
+// fused into the sweep).
+template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
+__device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
+                                          int z, int y0w, int seg, int yend, int xw) {
   using T = typename Stor<PREC>::T;
   const T* __restrict__ src = (const T*)A.src;
   T* __restrict__ dst = (T*)A.dst;
+  const int lane = threadIdx.x & 63;
   const int a = B.dim[0], b = B.dim[1], c = B.dim[2];
-  uint32_t m = 0;
+  const int r = lane / xw;
+  const int xl = lane - r * xw;
+  const int x0 = seg * 64 * VEC + xl * VEC;
+  const int y = y0w + r;
+  // Every lane of a live row takes part in the shuffles below; a lane only
+  // ever reads a neighbour lane of its own live row.
+  if (x0 >= a || y >= yend) return;
+  const bool first = xl == 0;
+  const bool last = (xl == xw - 1) || (x0 + VEC >= a);
+
+  uint32_t m[VEC];
+  bool solid[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    m[k] = 0;
+    solid[k] = false;
+  }
   if constexpr (MASK) {
-    m = A.mask[B.mask + ((long long)z * b + y) * a + x];
-    if (m & kSolidBit) return;
+    const uint32_t* mp = A.mask + B.mask + ((long long)z * b + y) * a + x0;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      m[k] = mp[k];
+      solid[k] = (m[k] & kSolidBit) != 0;
+    }
   }
-  const int gx = B.org[0] + x, gy = B.org[1] + y, gz = B.org[2] + z;
-  const bool lox = A.geo.wall[0] && gx == 0, hix = A.geo.wall[0] && gx == A.geo.n[0] - 1;
-  const bool loy = A.geo.wall[1] && gy == 0, hiy = A.geo.wall[1] && gy == A.geo.n[1] - 1;
-  const bool loz = A.geo.wall[2] && gz == 0, hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
-  const long long cell = main_off(B, 0, x, y, z);
-  const long long xrow = (long long)(z + 1) * B.Ry + (y + 1);
+  const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx + seg * 64 * VEC;
+  const uint32_t lo = (uint32_t)(r * B.Sx + xl * VEC);
+  const uint32_t lob = lo * (uint32_t)sizeof(T);
+  const int gx0 = B.org[0] + x0, gy = B.org[1] + y, gz = B.org[2] + z;
+  WallFlags wf;
+  wf.lox = A.geo.wall[0] && gx0 == 0;
+  wf.hix = A.geo.wall[0] && gx0 + VEC - 1 == A.geo.n[0] - 1;
+  wf.loy = A.geo.wall[1] && gy == 0;
+  wf.hiy = A.geo.wall[1] && gy == A.geo.n[1] - 1;
+  wf.loz = A.geo.wall[2] && gz == 0;
+  wf.hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
+  const bool moving = A.geo.moving[0] | A.geo.moving[1] | A.geo.moving[2] | A.geo.moving[3] | A.geo.moving[4] |
+                      A.geo.moving[5];
 
-  C f[kQ];
+  // ---- pull: W[i][k] = stored value that cell k receives along e_i
+  T W[kQ][VEC];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
-    if (i == 0) {
-      f[0] = to_c<PREC, C>(ld<T, NT>(src + cell));
-      continue;
+    const T* pb = src + (rb + (long long)i * B.Sf - (long long)ez * B.Sz - (long long)ey * B.Sx);
+    if constexpr (VEC == 1) {
+      // one cell per lane: the x-shifted pull is a plain load at x - e_x
+      T v = ldo<T, NT>(pb - ex, lob);
+      if (ex > 0 && x0 == 0)
+        v = ld<T, NT>(src + B.xg + (long long)KLOd(i) * B.P + (long long)(z + 1 - ez) * B.Ry + (y + 1 - ey));
+      if (ex < 0 && x0 == a - 1)
+        v = ld<T, NT>(src + B.xg + (long long)(5 + KHId(i)) * B.P + (long long)(z + 1 - ez) * B.Ry +
+                      (y + 1 - ey));
+      W[i][0] = v;
+    } else {
+    T V[VEC];
+    vld<T, VEC, NT>(pb, lob, V);
+    if (ex == 0) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) W[i][k] = V[k];
+    } else if (ex > 0) {  // source x - 1
+#pragma unroll
+      for (int k = VEC - 1; k > 0; --k) W[i][k] = V[k - 1];
+      T e = sh_up(V[VEC - 1]);
+      if (first) {
+        if (x0 == 0)
+          e = ld<T, NT>(src + B.xg + (long long)KLOd(i) * B.P + (long long)(z + 1 - ez) * B.Ry + (y + 1 - ey));
+        else
+          e = ld<T, NT>(pb + (long long)lo - 1);
+      }
+      W[i][0] = e;
+    } else {  // source x + 1
+#pragma unroll
+      for (int k = 0; k < VEC - 1; ++k) W[i][k] = V[k + 1];
+      T e = sh_down(V[0]);
+      if (last) {
+        if (x0 + VEC == a)
+          e = ld<T, NT>(src + B.xg + (long long)(5 + KHId(i)) * B.P + (long long)(z + 1 - ez) * B.Ry +
+                        (y + 1 - ey));
+        else
+          e = ld<T, NT>(pb + (long long)lo + VEC);
+      }
+      W[i][VEC - 1] = e;
     }
-    // source beyond a wall face -> wall link
-    bool bw = false;
-    if (ex > 0) bw = bw || lox;
-    if (ex < 0) bw = bw || hix;
-    if (ey > 0) bw = bw || loy;
-    if (ey < 0) bw = bw || hiy;
-    if (ez > 0) bw = bw || loz;
-    if (ez < 0) bw = bw || hiz;
-    bool bb = bw;
-    if constexpr (MASK) bb = bb || ((m >> i) & 1u);
-    long long off = cell + (long long)i * B.Sf - (long long)ez * B.Sz - (long long)ey * B.Sx - ex;
-    if (ex > 0 && x == 0) off = B.xg + (long long)KLOd(i) * B.P + xrow - (long long)ez * B.Ry - ey;
-    if (ex < 0 && x == a - 1) off = B.xg + (long long)(5 + KHId(i)) * B.P + xrow - (long long)ez * B.Ry - ey;
-    if (bb) off = cell + (long long)OPPd(i) * B.Sf;
-    C v = to_c<PREC, C>(ld<T, NT>(src + off));
-    if (bw) {
-      // velocity of the first moving face, order -x,+x,-y,+y,-z,+z
-      C cw = (C)0;
-      if (ez != 0 && (ez > 0 ? loz : hiz) && A.geo.moving[ez > 0 ? 4 : 5]) cw = ph.corr[i][ez > 0 ? 4 : 5];
-      if (ey != 0 && (ey > 0 ? loy : hiy) && A.geo.moving[ey > 0 ? 2 : 3]) cw = ph.corr[i][ey > 0 ? 2 : 3];
-      if (ex != 0 && (ex > 0 ? lox : hix) && A.geo.moving[ex > 0 ? 0 : 1]) cw = ph.corr[i][ex > 0 ? 0 : 1];
-      v += cw;
     }
-    f[i] = v;
+    if (i > 0) {
+      // bounce-back links take the cell's own opposite population
+      bool any = false;
+      bool bbk[VEC];
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        bbk[k] = wall_link<VEC>(wf, i, k);
+        if constexpr (MASK) bbk[k] = bbk[k] || ((m[k] >> i) & 1u);
+        any = any || bbk[k];
+      }
+      if (any) {
+        T O[VEC];
+        vld<T, VEC, NT>(src + (rb + (long long)OPPd(i) * B.Sf), lob, O);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          if (bbk[k]) {
+            W[i][k] = O[k];
+            // storage and arithmetic types agree: the moving-wall term is
+            // added here, exactly as in arithmetic precision
+            if constexpr (kSameType<T, C>)
+              if (moving && wall_link<VEC>(wf, i, k)) W[i][k] = O[k] + wall_corr<C, VEC>(A, ph, wf, i, k);
+          }
+        }
+      }
+    }
   }
 
-  // moments (Sec. 2.1): drho = sum f~, rho0 u = sum e f~, plus half force
-  C drho = (C)0, jx = (C)0, jy = (C)0, jz = (C)0;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    drho += f[i];
-    if (EXd(i) > 0) jx += f[i];
-    if (EXd(i) < 0) jx -= f[i];
-    if (EYd(i) > 0) jy += f[i];
-    if (EYd(i) < 0) jy -= f[i];
-    if (EZd(i) > 0) jz += f[i];
-    if (EZd(i) < 0) jz -= f[i];
-  }
-  const C ux = fma(jx, ph.inv_rho0, ph.hg[0]);
-  const C uy = fma(jy, ph.inv_rho0, ph.hg[1]);
-  const C uz = fma(jz, ph.inv_rho0, ph.hg[2]);
-  const C uu15 = (C)1.5 * fma(ux, ux, fma(uy, uy, uz * uz));
-  const C ug = fma(ux, ph.g[0], fma(uy, ph.g[1], uz * ph.g[2]));
+  // value of population i at element k in arithmetic precision; with a
+  // narrower storage type the moving-wall term of a wall link is added here
+  auto fval = [&](int i, int k) -> C {
+    C v = to_c<PREC, C>(W[i][k]);
+    if constexpr (!kSameType<T, C>)
+      if (moving && i > 0 && wall_link<VEC>(wf, i, k)) v += wall_corr<C, VEC>(A, ph, wf, i, k);
+    return v;
+  };
 
-  const bool edge = FUSED && ((x == 0) | (x == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
+  // ---- moments (Sec. 2.1): drho = sum f~, rho0 u = sum e f~, plus half force
+  C drho[VEC], ux[VEC], uy[VEC], uz[VEC], uu15[VEC], ug3[VEC];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
-    const C w = (C)Wd(i);
-    C eu = (C)0, eg = (C)0;
-    if (ex > 0) { eu += ux; eg += ph.g[0]; }
-    if (ex < 0) { eu -= ux; eg -= ph.g[0]; }
-    if (ey > 0) { eu += uy; eg += ph.g[1]; }
-    if (ey < 0) { eu -= uy; eg -= ph.g[1]; }
-    if (ez > 0) { eu += uz; eg += ph.g[2]; }
-    if (ez < 0) { eu -= uz; eg -= ph.g[2]; }
-    // feq~ = w [drho + rho0 (3 eu + 4.5 eu^2 - 1.5 u.u)],  F = w rho0 [3 (eg - ug) + 9 eu eg]
-    const C feq = w * fma(ph.rho0, fma((C)4.5 * eu, eu, (C)3 * eu - uu15), drho);
-    const C F = (w * ph.rho0) * fma((C)9 * eu, eg, (C)3 * (eg - ug));
-    const C post = fma(ph.fcoef, F, fma(-ph.omega, f[i] - feq, f[i]));
-    const T out = from_c<PREC, C>(post);
-    st<T, NT>(dst + cell + (long long)i * B.Sf, out);
-    if (FUSED && i > 0 && edge) {
-      // x + e_i pulls f_i from x in the next step: outside this Block, the
-      // value goes to the ghost layer of the Block that owns x + e_i
-      const int cx = (ex > 0 && x == a - 1) ? 1 : ((ex < 0 && x == 0) ? -1 : 0);
-      const int cy = (ey > 0 && y == b - 1) ? 1 : ((ey < 0 && y == 0) ? -1 : 0);
-      const int cz = (ez > 0 && z == c - 1) ? 1 : ((ez < 0 && z == 0) ? -1 : 0);
-      if ((cx | cy | cz) != 0) {
-        const NbrDev nb = A.nbr[bid * 27 + 13 + cx + 3 * cy + 9 * cz];
-        if (nb.id >= 0) {
-          const BlockDev& M = A.blocks[nb.id];
-          const int xm = x + nb.tx, ym = y + nb.ty, zm = z + nb.tz;
-          long long o;
-          if (ex > 0 && xm < 0)
-            o = M.xg + (long long)KLOd(i) * M.P + (long long)(zm + 1) * M.Ry + (ym + 1);
-          else if (ex < 0 && xm >= M.dim[0])
-            o = M.xg + (long long)(5 + KHId(i)) * M.P + (long long)(zm + 1) * M.Ry + (ym + 1);
-          else
-            o = main_off(M, i, xm, ym, zm);
-          dst[o] = out;
+  for (int k = 0; k < VEC; ++k) {
+    C d = fval(0, k), jx = (C)0, jy = (C)0, jz = (C)0;
+#pragma unroll
+    for (int i = 1; i < kQ; i += 2) {  // (i, i+1) are opposite directions
+      const C fa = fval(i, k), fb = fval(i + 1, k);
+      const C sp = fa + fb, dp = fa - fb;
+      d += sp;
+      if (EXd(i) > 0) jx += dp;
+      if (EXd(i) < 0) jx -= dp;
+      if (EYd(i) > 0) jy += dp;
+      if (EYd(i) < 0) jy -= dp;
+      if (EZd(i) > 0) jz += dp;
+      if (EZd(i) < 0) jz -= dp;
+    }
+    drho[k] = d;
+    ux[k] = fma(jx, ph.inv_rho0, ph.hg[0]);
+    uy[k] = fma(jy, ph.inv_rho0, ph.hg[1]);
+    uz[k] = fma(jz, ph.inv_rho0, ph.hg[2]);
+    uu15[k] = (C)1.5 * fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
+    ug3[k] = ph.rho0x3 * fma(ux[k], ph.g[0], fma(uy[k], ph.g[1], uz[k] * ph.g[2]));
+  }
+
+  // ---- collision and stores
+  bool edge[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k)
+    edge[k] = FUSED && !solid[k] &&
+              ((x0 + k == 0) | (x0 + k == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
+  {
+    T o[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      // rest: feq~_0 = w0 (drho + rho0 (-1.5 u.u)), F_0 = w0 rho0 (-3 u.g)
+      const C feq = ph.w[0] * fma(ph.rho0, -uu15[k], drho[k]);
+      const C F = -ph.w[0] * ug3[k];
+      const C post = fma(ph.omc, fval(0, k), fma(ph.omega, feq, ph.fcoef * F));
+      o[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(post);
+    }
+    vst<T, VEC, NT>(dst + rb, lob, o);
+  }
+#pragma unroll
+  for (int i = 1; i < kQ; i += 2) {
+    T o0[VEC], o1[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      C eu = (C)0;
+      if (EXd(i) > 0) eu += ux[k];
+      if (EXd(i) < 0) eu -= ux[k];
+      if (EYd(i) > 0) eu += uy[k];
+      if (EYd(i) < 0) eu -= uy[k];
+      if (EZd(i) > 0) eu += uz[k];
+      if (EZd(i) < 0) eu -= uz[k];
+      // even part (shared by i and its opposite) and odd part (flips sign)
+      const C sym = ph.w[i] * fma(ph.rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
+      const C asym = ph.c3w[i] * eu;
+      const C Fs = fma(ph.c9g[i], eu, -ph.w[i] * ug3[k]);
+      const C even = fma(ph.omega, sym, ph.fcoef * Fs);
+      const C odd = fma(ph.omega, asym, ph.cfa[i]);
+      o0[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(fma(ph.omc, fval(i, k), even + odd));
+      o1[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(fma(ph.omc, fval(i + 1, k), even - odd));
+    }
+    vst<T, VEC, NT>(dst + (rb + (long long)i * B.Sf), lob, o0);
+    vst<T, VEC, NT>(dst + (rb + (long long)(i + 1) * B.Sf), lob, o1);
+    if constexpr (FUSED) {
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        if (!edge[k]) continue;
+        const int x = x0 + k;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int q = i + h;
+          const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
+          // x + e_q pulls f_q from x next step; outside this Block the value
+          // goes to the ghost layer of the Block that owns x + e_q
+          const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
+          const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
+          const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
+          if ((cx | cy | cz) != 0) {
+            const GhostTgt& G = A.ghost[bid * 27 + 13 + cx + 3 * cy + 9 * cz];
+            const T v = h == 0 ? o0[k] : o1[k];
+            if (G.kind == 1) {
+              dst[G.main0 + (long long)q * G.Sf + (long long)z * G.Sz + (long long)y * G.Sx + x] = v;
+            } else if (G.kind == 2) {
+              const int slot = qx > 0 ? KLOd(q) : KHId(q);
+              dst[G.xg0 + (long long)slot * G.P + (long long)z * G.Ry + y] = v;
+            }
+          }
         }
       }
     }
   }
 }
 
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT>
-__global__ void __launch_bounds__(1024) k_sweep(const SweepArgs A, const Phys<C> ph) {
+// At least 4 (one cell per lane) or 3 (several cells per lane) waves per
+// SIMD: enough bytes in flight per compute unit without spilling.
+template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
+k_sweep(const SweepArgs A, const Phys<C> ph) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const ItemDev item = A.items[it];
     const BlockDev B = A.blocks[item.block];
     const int a = B.dim[0];
-    const int ncell = item.nrows * a;
-    for (int L = threadIdx.x; L < ncell; L += blockDim.x) {
-      const int r = L / a;
-      sweep_cell<PREC, C, MASK, FUSED, NT>(A, ph, B, item.block, L - r * a, item.y0 + r, item.z);
+    const int lanes = (a + VEC - 1) / VEC;  // lanes per row
+    int xw = 64;
+    while (xw > 1 && xw / 2 >= lanes) xw >>= 1;
+    const int rpw = 64 / xw;                      // rows per wave
+    const int nseg = (lanes + 63) >> 6;           // 64-lane segments per row
+    const int ngroups = (item.nrows + rpw - 1) / rpw;
+    const int ntask = ngroups * nseg;
+    const int yend = item.y0 + item.nrows;
+    for (int t = wv; t < ntask; t += nw) {
+      const int grp = t / nseg, seg = t - grp * nseg;
+      sweep_row<PREC, C, MASK, FUSED, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw);
     }
   }
 }
@@ -502,32 +709,43 @@ __global__ void __launch_bounds__(256) k_copy16(const u32x4* __restrict__ src, u
 // ------------------------------------------------------------- launchers
 using SweepFn = void (*)(SweepArgs, Phys<double>, Phys<float>, dim3, dim3, hipStream_t);
 
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT>
+template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
 static void launch_sweep_t(SweepArgs a, Phys<double> pd, Phys<float> pf, dim3 g, dim3 b, hipStream_t s) {
   if constexpr (sizeof(C) == 8)
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT>), g, b, 0, s, a, pd);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT, VEC>), g, b, 0, s, a, pd);
   else
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT>), g, b, 0, s, a, pf);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT, VEC>), g, b, 0, s, a, pf);
 }
 
-template <int PREC, typename C>
+template <int PREC, typename C, int VEC>
 static SweepFn pick3(bool mask, bool fused, bool nt) {
   if (mask) {
-    if (fused) return nt ? launch_sweep_t<PREC, C, true, true, true> : launch_sweep_t<PREC, C, true, true, false>;
-    return nt ? launch_sweep_t<PREC, C, true, false, true> : launch_sweep_t<PREC, C, true, false, false>;
+    if (fused) return nt ? launch_sweep_t<PREC, C, true, true, true, VEC> : launch_sweep_t<PREC, C, true, true, false, VEC>;
+    return nt ? launch_sweep_t<PREC, C, true, false, true, VEC> : launch_sweep_t<PREC, C, true, false, false, VEC>;
   }
-  if (fused) return nt ? launch_sweep_t<PREC, C, false, true, true> : launch_sweep_t<PREC, C, false, true, false>;
-  return nt ? launch_sweep_t<PREC, C, false, false, true> : launch_sweep_t<PREC, C, false, false, false>;
+  if (fused) return nt ? launch_sweep_t<PREC, C, false, true, true, VEC> : launch_sweep_t<PREC, C, false, true, false, VEC>;
+  return nt ? launch_sweep_t<PREC, C, false, false, true, VEC> : launch_sweep_t<PREC, C, false, false, false, VEC>;
 }
 
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, const SweepArgs& a,
+// Cells per lane along x: 8 bytes of storage per lane and stream when every
+// Block's x extent allows it (vec_ok), else one.
+int sweep_vec(int prec, bool vec_ok) {
+  if (!vec_ok) return 1;
+  return prec == 0 ? 1 : (prec == 1 ? 2 : 4);
+}
+
+void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
+  const bool v = sweep_vec(prec, vec_ok) > 1;
   switch (prec) {
-    case 0: fn = pick3<0, double>(mask, fused, nt); break;
-    case 1: fn = f64math ? pick3<1, double>(mask, fused, nt) : pick3<1, float>(mask, fused, nt); break;
-    case 2: fn = pick3<2, float>(mask, fused, nt); break;
-    default: fn = pick3<3, float>(mask, fused, nt); break;
+    case 0: fn = pick3<0, double, 1>(mask, fused, nt); break;
+    case 1:
+      if (f64math) fn = v ? pick3<1, double, 2>(mask, fused, nt) : pick3<1, double, 1>(mask, fused, nt);
+      else fn = v ? pick3<1, float, 2>(mask, fused, nt) : pick3<1, float, 1>(mask, fused, nt);
+      break;
+    case 2: fn = v ? pick3<2, float, 4>(mask, fused, nt) : pick3<2, float, 1>(mask, fused, nt); break;
+    default: fn = v ? pick3<3, float, 4>(mask, fused, nt) : pick3<3, float, 1>(mask, fused, nt); break;
   }
   fn(a, pd, pf, grid, block, s);
 }

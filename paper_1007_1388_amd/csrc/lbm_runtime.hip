@@ -23,8 +23,9 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
+int sweep_vec(int prec, bool vec_ok);
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
                      int ntasks, int max_cells, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
@@ -101,11 +102,13 @@ struct lbm_ctx {
   size_t grid_elems = 0;
   BlockDev* d_blocks = nullptr;
   NbrDev* d_nbr = nullptr;
+  GhostTgt* d_ghost = nullptr;
   ItemDev* d_items = nullptr;
   size_t items_cap = 0;
   XchgTask* d_tasks = nullptr;
   uint32_t* d_mask = nullptr;
   bool has_mask = false;
+  bool vec_ok = false;   // every Block's x extent is a multiple of the vector width
   double* d_partial = nullptr;
   int nparts = 1024;
   double* d_red = nullptr;
@@ -299,9 +302,35 @@ SweepArgs sweep_args(const lbm_ctx* c, int from) {
   a.nbr = c->d_nbr;
   a.items = c->d_items;
   a.mask = c->d_mask;
+  a.ghost = c->d_ghost;
   a.nitems = (int)c->items_h.size();
   a.geo = c->geo;
   return a;
+}
+
+// Ghost-target table of the fused exchange: for Block j and offset class d,
+// where the boundary values of j land in neighbour M (see GhostTgt).
+std::vector<GhostTgt> build_ghost_table(const lbm_ctx* c) {
+  const int nb = (int)c->bh.size();
+  std::vector<GhostTgt> t((size_t)nb * 27);
+  for (int j = 0; j < nb; ++j)
+    for (int d = 0; d < 27; ++d) {
+      GhostTgt& g = t[(size_t)j * 27 + d];
+      std::memset(&g, 0, sizeof(g));
+      const NbrDev& n = c->nbh[(size_t)j * 27 + d];
+      if (d == 13 || n.id < 0) continue;
+      const BlockDev& M = c->bh[n.id];
+      const int cx = d % 3 - 1;
+      g.Sz = M.Sz;
+      g.Sf = M.Sf;
+      g.Sx = M.Sx;
+      g.Ry = M.Ry;
+      g.P = M.P;
+      g.main0 = M.base + (long long)(n.tz + 1) * M.Sz + (long long)(n.ty + 1) * M.Sx + n.tx;
+      g.xg0 = M.xg + (cx < 0 ? 5LL * M.P : 0LL) + (long long)(n.tz + 1) * M.Ry + (n.ty + 1);
+      g.kind = cx == 0 ? 1 : 2;
+    }
+  return t;
 }
 
 void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s) {
@@ -315,8 +344,8 @@ void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
   int grid = nitems;
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
-  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0, a,
-               c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0,
+               c->vec_ok, a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
   if (!c->sched.fused_exchange) enqueue_exchange(c, 1 - from, s);
 }
 
@@ -425,8 +454,8 @@ std::string sched_str(const lbm_schedule& s) {
 
 bool sched_valid(const lbm_schedule& s, std::string& err) {
   const int wg = s.wg_size;
-  if (!(wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024)) {
-    err = "wg_size must be 64, 128, 256, 512 or 1024";
+  if (!(wg == 64 || wg == 128 || wg == 256)) {
+    err = "wg_size must be 64, 128 or 256";
     return false;
   }
   if (s.item_cells < 1 || s.item_cells > (1 << 22)) {
@@ -538,16 +567,46 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       const double eu = E3[i][0] * p->wall_u[f][0] + E3[i][1] * p->wall_u[f][1] + E3[i][2] * p->wall_u[f][2];
       c->phd.corr[i][f] = 6.0 * weight(i) * p->rho0 * eu;
     }
+  c->phd.omc = 1.0 - omega;
+  c->phd.rho0x3 = 3.0 * p->rho0;
+  for (int i = 0; i < kQ; ++i) {
+    const double eg = E3[i][0] * p->force[0] + E3[i][1] * p->force[1] + E3[i][2] * p->force[2];
+    c->phd.w[i] = weight(i);
+    c->phd.c3w[i] = 3.0 * weight(i) * p->rho0;
+    c->phd.c9g[i] = 9.0 * weight(i) * p->rho0 * eg;
+    c->phd.cfa[i] = c->phd.fcoef * 3.0 * weight(i) * p->rho0 * eg;
+  }
   c->phf.omega = (float)c->phd.omega;
+  c->phf.omc = (float)c->phd.omc;
   c->phf.rho0 = (float)c->phd.rho0;
   c->phf.inv_rho0 = (float)c->phd.inv_rho0;
   c->phf.fcoef = (float)c->phd.fcoef;
+  c->phf.rho0x3 = (float)c->phd.rho0x3;
   for (int k = 0; k < 3; ++k) {
     c->phf.g[k] = (float)c->phd.g[k];
     c->phf.hg[k] = (float)c->phd.hg[k];
   }
-  for (int i = 0; i < kQ; ++i)
-    for (int f = 0; f < 6; ++f) c->phf.corr[i][f] = (float)c->phd.corr[i][f];
+  // FP32 constants chosen so that the discrete moment identities hold
+  // exactly for the rounded values: sum_i w_i = 1 and sum_i 3 w_i e_i e_i = I
+  // (edge constant rounded, face constant solved from it).  Plain rounding of
+  // 1/18, 1/36 leaves a relative bias of ~3e-8 in every step's momentum
+  // relaxation, which accumulates over thousands of steps.
+  {
+    const float we = (float)(1.0 / 36.0);
+    const float wf = 2.0f * we;
+    const float w0 = (float)(1.0 - 6.0 * (double)wf - 12.0 * (double)we);
+    const float c3e = (float)(3.0 / 36.0 * p->rho0);
+    const float c3f = (float)((p->rho0 - 8.0 * (double)c3e) / 2.0);
+    for (int i = 0; i < kQ; ++i) {
+      const int s2 = E3[i][0] * E3[i][0] + E3[i][1] * E3[i][1] + E3[i][2] * E3[i][2];
+      const double eg = E3[i][0] * p->force[0] + E3[i][1] * p->force[1] + E3[i][2] * p->force[2];
+      c->phf.w[i] = s2 == 0 ? w0 : (s2 == 1 ? wf : we);
+      c->phf.c3w[i] = s2 == 0 ? 0.0f : (s2 == 1 ? c3f : c3e);
+      c->phf.c9g[i] = (float)(3.0 * (double)c->phf.c3w[i] * eg);
+      c->phf.cfa[i] = (float)(c->phd.fcoef * (double)c->phf.c3w[i] * eg);
+      for (int f = 0; f < 6; ++f) c->phf.corr[i][f] = (float)c->phd.corr[i][f];
+    }
+  }
 
   // per-Block layout (see lbm_internal.h)
   const long long align = 128 / c->sbytes;  // elements per 128-byte line
@@ -573,6 +632,12 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     B.mask = -1;
   }
   c->grid_elems = (size_t)off;
+  {
+    const int vw = sweep_vec(c->prec, true);
+    c->vec_ok = true;
+    for (const auto& B : c->bh)
+      if (B.dim[0] % vw) c->vec_ok = false;
+  }
 
   // neighbour table: Block across each face/edge/corner, with translation
   c->nbh.assign((size_t)nblocks * 27, NbrDev{-1, 0, 0, 0});
@@ -621,13 +686,17 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->grid[1] = dalloc(c, gbytes);
   c->d_blocks = (BlockDev*)dalloc(c, sizeof(BlockDev) * nblocks);
   c->d_nbr = (NbrDev*)dalloc(c, sizeof(NbrDev) * c->nbh.size());
+  c->d_ghost = (GhostTgt*)dalloc(c, sizeof(GhostTgt) * c->nbh.size());
   c->d_tasks = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->tasks_h.size()));
   c->d_partial = (double*)dalloc(c, sizeof(double) * 6 * c->nparts);
   c->d_red = (double*)dalloc(c, sizeof(double) * 8);
-  if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_tasks || !c->d_partial || !c->d_red)
+  if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_partial ||
+      !c->d_red)
     return bail(LBM_ENOMEM, "device allocation failed");
   if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_ghost, build_ghost_table(c).data(), sizeof(GhostTgt) * c->nbh.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
       (!c->tasks_h.empty() && hipMemcpy(c->d_tasks, c->tasks_h.data(), sizeof(XchgTask) * c->tasks_h.size(),
                                         hipMemcpyHostToDevice) != hipSuccess))
     return bail(LBM_EDEVICE, "upload of block tables failed");
@@ -887,7 +956,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
   lbm_status st = timeit(best, &best_ms);
   // coordinate descent over the schedule knobs
   const std::vector<int> cells = {128, 256, 512, 1024, 2048, 4096};
-  const std::vector<int> wgs = {128, 256, 512, 1024};
+  const std::vector<int> wgs = {64, 128, 256};
   const std::vector<int> pers = {0, 2, 4, 8, 16};
   for (int pass = 0; pass < 2 && st == LBM_OK; ++pass) {
     for (int knob = 0; knob < 5 && st == LBM_OK; ++knob) {

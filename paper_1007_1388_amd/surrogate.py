@@ -86,6 +86,7 @@ class Act:
         else:
             self.buf, self.off, self.ldc = buf, off, ldc
         self.t5 = lbm_tensor5(self.buf.data_ptr() + 2 * self.off, n, d, h, w, c, self.ldc)
+        self.t5._owner = self   # a byref of t5 keeps the buffer alive
 
     def slice(self, off, c):
         return Act(self.n, self.d, self.h, self.w, c, buf=self.buf, off=self.off + off, ldc=self.ldc)

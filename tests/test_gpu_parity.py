@@ -47,7 +47,12 @@ def check_vs_oracle(lat, o, tol):
     rho_o, u_o = o.macroscopic()
     err = field_errors(rho_g, u_g, rho_o, u_o)
     assert err["u_inf"] <= tol and err["drho_inf"] <= tol, err
-    fs = rel_inf(lat.get_state(), o.get_state())
+    # Populations: a post-collision value sums terms as large as the force
+    # source 3 w rho0 |g| even when the result is much smaller, so rounding is
+    # measured against max(|f|, rho0 |g|).
+    fg, fo = lat.get_state(), o.get_state()
+    scale = max(np.abs(fo).max(), o.rho0 * np.abs(np.asarray(o.force)).max())
+    fs = np.abs(fg - fo).max() / scale
     assert fs <= tol, fs
     return err
 
@@ -120,13 +125,16 @@ TILINGS = {
     "slabs": lambda d: inputs.uniform_blocks(d, (1, 1, 4)),
     "random": lambda d: inputs.random_tiling(d, max_blocks_per_axis=4, seed=3, min_edge=1),
     "thin": lambda d: inputs.uniform_blocks(d, (d[0], 1, 1)),
+    "vec": lambda d: inputs.uniform_blocks(d, (max(1, d[0] // 8), 2, 3)),
 }
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s", "bf16s"])
 @pytest.mark.parametrize("tiling", sorted(TILINGS))
-def test_partition_invariance_bitwise(precision, tiling):
-    dims = (13, 12, 10)
+@pytest.mark.parametrize("dims", [(13, 12, 10), (24, 12, 10)])
+def test_partition_invariance_bitwise(precision, tiling, dims):
+    # x = 24 lets the single Block use several cells per lane; most tilings
+    # then fall back to one cell per lane: both must round alike.
     solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 3), seed=2)
     case = channel(dims=dims, solid=solid, force=(1e-5, 0, 3e-6), tau=0.75, seed=4)
     ref = run_gpu(case, 25, precision=precision)
@@ -137,7 +145,7 @@ def test_partition_invariance_bitwise(precision, tiling):
 SCHEDULES = [
     dict(fused_exchange=0),
     dict(fused_exchange=1, persistent=2, wg_size=128, item_cells=64),
-    dict(fused_exchange=0, persistent=1, wg_size=1024, item_cells=4096, nontemporal=0),
+    dict(fused_exchange=0, persistent=1, wg_size=64, item_cells=4096, nontemporal=0),
     dict(graph_steps=4),
     dict(graph_steps=3, fused_exchange=0),
 ]

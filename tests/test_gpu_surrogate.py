@@ -1,0 +1,258 @@
+"""GPU checks of the surrogate kernels against the FP64 reference (oracle.conv).
+
+Inputs are rounded to BF16 on the host first, so both sides see the same
+operands; the GPU accumulates in FP32 and rounds its output to BF16, which
+bounds the difference by ~2^-8 of the output scale (forward, input gradient)
+and by FP32 summation error (weight gradient)."""
+import numpy as np
+import pytest
+
+from oracle import conv
+
+pytestmark = pytest.mark.gpu
+
+
+def _sur():
+    from paper_1007_1388_amd import surrogate
+    return surrogate
+
+
+def bf(a):
+    return conv.bf16_round(a)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+CASES = [
+    dict(n=2, d=6, h=8, w=10, ci=16, co=24, k=3, s=1),
+    dict(n=1, d=8, h=6, w=4, ci=8, co=32, k=3, s=2),
+    dict(n=1, d=5, h=7, w=9, ci=64, co=80, k=3, s=1),
+    dict(n=2, d=4, h=4, w=6, ci=32, co=8, k=1, s=1),
+    dict(n=1, d=9, h=3, w=5, ci=24, co=16, k=3, s=2),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("relu", [False, True])
+def test_conv_forward(case, relu):
+    S = _sur()
+    c = CASES[case]
+    rng = np.random.default_rng(case)
+    x = bf(rng.standard_normal((c["n"], c["d"], c["h"], c["w"], c["ci"])))
+    w = bf(rng.standard_normal((c["co"], c["k"] ** 3, c["ci"])) * 0.1)
+    b = rng.standard_normal(c["co"]).astype(np.float32) * 0.1
+    layer = S.Conv(c["ci"], c["co"], k=c["k"], stride=c["s"], relu=relu)
+    layer.set_weights(w, b)
+    X = S.from_numpy(x)
+    ref = conv.conv3d(x, w, b.astype(np.float64), c["k"], c["s"], relu)
+    Y = S.Act(c["n"], *ref.shape[1:4], c["co"])
+    layer.forward(X, Y)
+    got = Y.to_numpy()
+    assert rel(got, ref) < 8e-3, rel(got, ref)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_conv_input_gradient_with_relu_mask(case):
+    S = _sur()
+    c = CASES[case]
+    rng = np.random.default_rng(10 + case)
+    xs = (c["n"], c["d"], c["h"], c["w"], c["ci"])
+    w = bf(rng.standard_normal((c["co"], c["k"] ** 3, c["ci"])) * 0.1)
+    layer = S.Conv(c["ci"], c["co"], k=c["k"], stride=c["s"], relu=False)
+    layer.set_weights(w, np.zeros(c["co"]))
+    ys = conv.conv3d(np.zeros(xs), w, None, c["k"], c["s"]).shape
+    dy = bf(rng.standard_normal(ys))
+    act = bf(rng.standard_normal(xs))       # ReLU'(act) masks the result
+    ref = conv.conv3d_bwd_data(dy, w, xs, c["k"], c["s"]) * (act > 0)
+    DX = S.Act(*xs)
+    from paper_1007_1388_amd.surrogate import lib
+    L = lib()
+    DY, ACT = S.from_numpy(dy), S.from_numpy(act)   # keep the buffers alive during the calls
+    st = L.lbm_conv3d_bwd_data(DY.ref, layer.wt.data_ptr(), DX.ref, ACT.ref, c["k"], c["s"], 0, None)
+    assert st == 0
+    got = DX.to_numpy()
+    assert rel(got, ref) < 8e-3, rel(got, ref)
+    # accumulate mode adds a second copy
+    prev = bf(rng.standard_normal(xs))
+    DX2 = S.from_numpy(prev)
+    st = L.lbm_conv3d_bwd_data(DY.ref, layer.wt.data_ptr(), DX2.ref, None, c["k"], c["s"], 1, None)
+    assert st == 0
+    ref2 = prev + conv.conv3d_bwd_data(dy, w, xs, c["k"], c["s"])
+    assert rel(DX2.to_numpy(), ref2) < 8e-3
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_conv_weight_gradient(case):
+    S = _sur()
+    c = CASES[case]
+    rng = np.random.default_rng(20 + case)
+    xs = (c["n"], c["d"], c["h"], c["w"], c["ci"])
+    x = bf(rng.standard_normal(xs))
+    layer = S.Conv(c["ci"], c["co"], k=c["k"], stride=c["s"], relu=False)
+    ys = conv.conv3d(x, np.zeros((c["co"], c["k"] ** 3, c["ci"])), None, c["k"], c["s"]).shape
+    dy = bf(rng.standard_normal(ys))
+    layer.zero_grad()
+    layer.backward(S.from_numpy(x), S.from_numpy(dy), None)
+    dw_ref, db_ref = conv.conv3d_bwd_weight(x, dy, c["k"], c["s"])
+    gw = layer.gw.cpu().numpy()[:, :c["k"] ** 3 * c["ci"]].reshape(dw_ref.shape)
+    assert rel(gw, dw_ref) < 1e-5, rel(gw, dw_ref)
+    assert rel(layer.gb.cpu().numpy(), db_ref) < 1e-5
+    assert np.all(layer.gw.cpu().numpy()[:, c["k"] ** 3 * c["ci"]:] == 0)
+
+
+def test_upsample_pair():
+    S = _sur()
+    from paper_1007_1388_amd.surrogate import lib
+    rng = np.random.default_rng(3)
+    x = bf(rng.standard_normal((2, 3, 2, 4, 16)))
+    X = S.from_numpy(x)
+    Y = S.Act(2, 6, 4, 8, 16)
+    assert lib().lbm_upsample2(X.ref, Y.ref, None) == 0
+    assert np.array_equal(Y.to_numpy(), conv.upsample2(x))
+    dy = bf(rng.standard_normal((2, 6, 4, 8, 16)))
+    DX = S.Act(2, 3, 2, 4, 16)
+    DY = S.from_numpy(dy)
+    assert lib().lbm_upsample2_bwd(DY.ref, DX.ref, 0, None) == 0
+    assert rel(DX.to_numpy(), conv.upsample2_bwd(dy)) < 8e-3
+
+
+def test_mse_and_adam():
+    import torch
+    S = _sur()
+    from paper_1007_1388_amd.surrogate import lib
+    rng = np.random.default_rng(4)
+    pred = bf(rng.standard_normal((1, 4, 4, 4, 8)))
+    tgt = rng.standard_normal((64, 4)).astype(np.float32)
+    wgt = (rng.random(64) > 0.3).astype(np.uint8)
+    P = S.from_numpy(pred)
+    D = S.Act(1, 4, 4, 4, 8)
+    t = torch.from_numpy(tgt).cuda()
+    wt = torch.from_numpy(wgt).cuda()
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    inv = 1.0 / (4 * wgt.sum())
+    assert lib().lbm_mse_loss(P.ref, t.data_ptr(), wt.data_ptr(), 4, inv, D.ref, loss.data_ptr(), None) == 0
+    p = pred.reshape(64, 8)[:, :4]
+    ref_loss = (((p - tgt) ** 2).sum(1) * wgt).sum() * inv
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+    g = D.to_numpy().reshape(64, 8)
+    ref_g = 2 * (p - tgt) * inv * wgt[:, None]
+    assert np.abs(g[:, :4] - ref_g).max() <= 8e-3 * np.abs(ref_g).max() and np.all(g[:, 4:] == 0)
+    # one Adam step from zero moments moves each weight by lr * sign(grad)
+    w = torch.zeros(100, device="cuda")
+    gr = torch.from_numpy(rng.standard_normal(100).astype(np.float32)).cuda()
+    m, v = torch.zeros_like(w), torch.zeros_like(w)
+    assert lib().lbm_adam_step(w.data_ptr(), gr.data_ptr(), m.data_ptr(), v.data_ptr(), 100, 1e-2, 0.9, 0.999,
+                               1e-12, 1, None) == 0
+    assert np.allclose(w.cpu().numpy(), -1e-2 * np.sign(gr.cpu().numpy()), rtol=1e-5, atol=1e-7)
+
+
+def _ref_unet(net, x):
+    """FP64 forward of the same network with oracle.conv, on BF16-rounded
+    weights (activations kept in FP64); returns all intermediate tensors."""
+    W = {}
+    for name in ("e0a e0b dn0 e1a e1b dn1 e2a e2b dn2 e3a e3b up2 d2a d2b up1 d1a d1b up0 d0a d0b head").split():
+        l = getattr(net, name)
+        w = l.w.cpu().numpy()[:, :l.taps * l.cin].reshape(l.cout, l.taps, l.cin).astype(np.float64)
+        W[name] = (bf(w), l.b.cpu().numpy().astype(np.float64), l.k, l.stride, l.relu)
+
+    def C(name, t):
+        w, b, k, s, r = W[name]
+        return conv.conv3d(t, w, b, k, s, r)
+
+    T = {}
+    T["a0"] = C("e0a", x)
+    T["s0"] = C("e0b", T["a0"])
+    T["l1"] = C("dn0", T["s0"])
+    T["a1"] = C("e1a", T["l1"])
+    T["s1"] = C("e1b", T["a1"])
+    T["l2"] = C("dn1", T["s1"])
+    T["a2"] = C("e2a", T["l2"])
+    T["s2"] = C("e2b", T["a2"])
+    T["l3"] = C("dn2", T["s2"])
+    T["a3"] = C("e3a", T["l3"])
+    T["b3"] = C("e3b", T["a3"])
+    T["u2"] = conv.upsample2(T["b3"])
+    T["c2"] = np.concatenate([C("up2", T["u2"]), T["s2"]], -1)
+    T["d2"] = C("d2a", T["c2"])
+    T["d2o"] = C("d2b", T["d2"])
+    T["u1"] = conv.upsample2(T["d2o"])
+    T["c1"] = np.concatenate([C("up1", T["u1"]), T["s1"]], -1)
+    T["d1"] = C("d1a", T["c1"])
+    T["d1o"] = C("d1b", T["d1"])
+    T["u0"] = conv.upsample2(T["d1o"])
+    T["c0"] = np.concatenate([C("up0", T["u0"]), T["s0"]], -1)
+    T["d0"] = C("d0a", T["c0"])
+    T["d0o"] = C("d0b", T["d0"])
+    T["pred"] = C("head", T["d0o"])
+    return W, T
+
+
+def _ref_grads(W, T, x, dpred):
+    """FP64 backward through the same graph (adjoints from oracle.conv)."""
+    G = {}
+
+    def back(name, xin, dout_post, out_post):
+        w, b, k, s, r = W[name]
+        dpre = dout_post * (out_post > 0) if r else dout_post
+        dw, db = conv.conv3d_bwd_weight(xin, dpre, k, s)
+        G[name] = (dw, db)
+        return conv.conv3d_bwd_data(dpre, w, xin.shape, k, s)
+
+    g = back("head", T["d0o"], dpred, T["pred"])
+    g = back("d0b", T["d0"], g, T["d0o"])
+    gc0 = back("d0a", T["c0"], g, T["d0"])
+    c0 = T["s0"].shape[-1]
+    up0_out = T["c0"][..., :c0]
+    g = back("up0", T["u0"], gc0[..., :c0], up0_out)
+    g = conv.upsample2_bwd(g)
+    g = back("d1b", T["d1"], g, T["d1o"])
+    gc1 = back("d1a", T["c1"], g, T["d1"])
+    c1 = T["s1"].shape[-1]
+    g = back("up1", T["u1"], gc1[..., :c1], T["c1"][..., :c1])
+    g = conv.upsample2_bwd(g)
+    g = back("d2b", T["d2"], g, T["d2o"])
+    gc2 = back("d2a", T["c2"], g, T["d2"])
+    c2 = T["s2"].shape[-1]
+    g = back("up2", T["u2"], gc2[..., :c2], T["c2"][..., :c2])
+    g = conv.upsample2_bwd(g)
+    g = back("e3b", T["a3"], g, T["b3"])
+    g = back("e3a", T["l3"], g, T["a3"])
+    g = back("dn2", T["s2"], g, T["l3"]) + gc2[..., c2:]
+    g = back("e2b", T["a2"], g, T["s2"])
+    g = back("e2a", T["l2"], g, T["a2"])
+    g = back("dn1", T["s1"], g, T["l2"]) + gc1[..., c1:]
+    g = back("e1b", T["a1"], g, T["s1"])
+    g = back("e1a", T["l1"], g, T["a1"])
+    g = back("dn0", T["s0"], g, T["l1"]) + gc0[..., c0:]
+    g = back("e0b", T["a0"], g, T["s0"])
+    back("e0a", x, g, T["a0"])
+    return G
+
+
+def test_whole_network_gradients_match_fp64_reference():
+    S = _sur()
+    rng = np.random.default_rng(7)
+    net = S.UNet(1, 16, 8, 8, seed=3)
+    x = np.zeros((1, 16, 8, 8, 8))
+    x[..., :3] = rng.standard_normal((1, 16, 8, 8, 3))
+    x = bf(x)
+    net.x.buf.copy_(S.from_numpy(x).buf)
+    pred = net.forward()
+    W, T = _ref_unet(net, x)
+    # BF16 activations on the GPU vs FP64 ones in the reference: a few 1e-2
+    assert rel(pred.to_numpy(), T["pred"]) < 1e-1, rel(pred.to_numpy(), T["pred"])
+    dpred = np.zeros_like(T["pred"])
+    dpred[..., :4] = bf(rng.standard_normal(dpred[..., :4].shape))
+    net.zero_grad()
+    net.backward(S.from_numpy(dpred))
+    G = _ref_grads(W, T, x, dpred)
+    worst = 0.0
+    for name, (dw, db) in G.items():
+        l = getattr(net, name)
+        gw = l.gw.cpu().numpy()[:, :l.taps * l.cin].reshape(dw.shape)
+        cos = (gw * dw).sum() / (np.linalg.norm(gw) * np.linalg.norm(dw) + 1e-300)
+        worst = max(worst, rel(gw, dw))
+        assert cos > 0.98, (name, cos)
+    assert worst < 0.2, worst

@@ -55,7 +55,7 @@ def workload(name):
     return p, blocks, solid
 
 
-def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=None):
+def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=None, autotune=None):
     import torch
     from paper_1007_1388_amd import lbm
     lat = lbm.Lattice(p["dims"], blocks=blocks, walls=p["walls"], wall_u=p["wall_u"], tau=p["tau"],
@@ -64,6 +64,8 @@ def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=Non
         lat.set_geometry(solid)
     if schedule:
         lat.set_schedule(**schedule)
+    if autotune:
+        lat.autotune(autotune, trial_steps=10)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -81,6 +83,18 @@ def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=Non
     mass, _ = lat.sums()   # finite-check of the run (raises on instability)
     lat.close()
     return dict(wall=wall, kernel_ms=gpu_ms / steps, info=info, schedule=sched, mass=mass)
+
+
+def copy_probe(nbytes=1 << 30, reps=10):
+    """Attainable HBM bandwidth of the library's 16-byte copy kernel (the
+    paper's own benchmark method, Sec. 3.1): GB/s counting read + write."""
+    import torch
+    from paper_1007_1388_amd import lbm
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    ms = lbm.lbm_bw_probe(b.data_ptr(), a.data_ptr(), nbytes, reps, torch.cuda.current_stream().cuda_stream)
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(p, solid, seconds=15.0):
@@ -114,9 +128,13 @@ def main():
     ap.add_argument("--workload", default="poiseuille256",
                     choices=["poiseuille256", "porous512", "cavity384", "cavity32"])
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
-    ap.add_argument("--fp64-math", type=int, default=1)
+    ap.add_argument("--fp64-math", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
+    ap.add_argument("--graph-steps", type=int, default=10, help="time steps per captured HIP graph")
+    ap.add_argument("--autotune", default=None, help="autotune cache file (runs the schedule autotuner)")
+    ap.add_argument("--copy-only", type=int, default=0,
+                    help="only run the copy probe on this many bytes (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the Block exchange between GPUs is a "
@@ -124,10 +142,16 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.init()
+    if args.copy_only:
+        gbs = copy_probe(args.copy_only, reps=1)
+        print(json.dumps({"copy_probe_bytes": args.copy_only, "copy_gbs": round(gbs, 1)}), flush=True)
+        return
+    copy_gbs = copy_probe()
     p, blocks, solid = workload(args.workload)
     prec = args.precision
     f64m = bool(args.fp64_math) and prec in ("f32", "f64")
-    r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup)
+    sched = {"graph_steps": args.graph_steps}
+    r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup, sched, args.autotune)
     info = r["info"]
     nf = info["n_fluid"]
     mlups = nf * args.steps / r["wall"] / 1e6
@@ -154,12 +178,13 @@ def main():
                    "fluid_cells": nf, "schedule": r["schedule"], "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                      "traffic": (round(tr / (r["kernel_ms"] * 1e-3) / 1e9, 1) if tr else None),
                      "kernel": "k_sweep", "kernel_ms": round(r["kernel_ms"], 5),
                      "bytes_per_update": bpu, "kernel_hash": src_hash},
     }
     if not args.no_f64 and prec == "f32":
-        r64 = time_gpu(p, blocks, solid, "f64", False, max(1, args.steps // 2), args.warmup)
+        r64 = time_gpu(p, blocks, solid, "f64", False, max(1, args.steps // 2), args.warmup, sched, args.autotune)
         i64 = r64["info"]
         m64 = i64["n_fluid"] * max(1, args.steps // 2) / r64["wall"] / 1e6
         a64 = i64["n_fluid"] * i64["bytes_per_update"] / (r64["kernel_ms"] * 1e-3) / 1e9

@@ -74,7 +74,9 @@ typedef struct {
   double rho0;            /* reference density, > 0 (1 for all presets) */
   double force[3];        /* body force g per unit mass, lattice units */
   int32_t precision;      /* lbm_precision */
-  int32_t fp64_math;      /* 1: FP64 arithmetic (F64 and F32 storage); F16S/BF16S ignore it */
+  int32_t fp64_math;      /* F32 storage: 1 = FP64 arithmetic, 0 = mixed (FP32 even part of the
+                             collision; FP64 velocity, odd part and update); F64 storage
+                             always FP64; F16S/BF16S always FP32 */
   void* stream;           /* hipStream_t; NULL = the null stream */
   void* (*dev_alloc)(size_t bytes, void* user);  /* optional device allocator */
   void (*dev_free)(void* ptr, void* user);

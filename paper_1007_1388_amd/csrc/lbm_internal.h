@@ -5,13 +5,18 @@
 // (Sec. 3.2): 19 arrays f_i[z][y][x] that include a one-cell ghost layer in y
 // and z (rows y = -1, b and planes z = -1, c), with x-rows padded to a
 // multiple of 128 bytes so every row starts on a cache line.  The ghost layer
-// in x (x = -1 and x = a) lives in ten separate planes, five per side, holding
-// only the five populations that cross an x face (Sec. 4.4 counts 5 PDFs per
-// face cell); keeping it out of the rows keeps the interior aligned.
+// in x lives in one extra plane per array, placed right after it: for the five
+// directions with e_x = +1 it holds x = -1, for the five with e_x = -1 it holds
+// x = a (Sec. 4.4 counts 5 PDFs per face cell).  Keeping the x ghosts out of
+// the rows keeps the interior aligned; keeping each plane next to its array
+// lets one scalar base plus a 32-bit lane offset reach both.
 //
-//   main:  base + i*Sf + (z+1)*Sz + (y+1)*Sx + x          0 <= x < a
-//   x-lo:  xg + k*P + (z+1)*Ry + (y+1)                    x = -1, k = klo(i)
-//   x-hi:  xg + (5+k)*P + (z+1)*Ry + (y+1)                x = a,  k = khi(i)
+//   main:    base + i*Sf + (z+1)*Sz + (y+1)*Sx + x          0 <= x < a
+//   x ghost: base + i*Sf + xgo + (z+1)*Ry + (y+1)            x = -1 or a
+//
+// Bounce-back slots: a population that would be pulled from beyond a wall or
+// from a solid cell is written there by the cell it bounces back to, so the
+// ghost/halo/solid slot of (x - e_i, i) holds f*_ibar(x) + 6 w_i rho0 e_i.u_w.
 //
 // Offsets are in elements of the storage type, relative to the grid pool.
 #pragma once
@@ -26,12 +31,10 @@ struct BlockDev {
   int org[3];       // global cell of the Block's (0,0,0)
   int Sx;           // x-row stride (elements)
   int Ry;           // b + 2: rows per plane of an x-ghost plane
-  int P;            // x-ghost plane stride (elements)
-  int pad0;
   long long Sz;     // Sx * (b + 2)
-  long long Sf;     // stride between the 19 population arrays
+  long long Sf;     // stride between the 19 population arrays (array + ghost plane)
+  long long xgo;    // offset of a population's x-ghost plane from the array start
   long long base;   // element offset of main[0][z=-1][y=-1][x=0]
-  long long xg;     // element offset of the 10 x-ghost planes
   long long mask;   // offset of the Block's link masks (a*b*c words), -1: none
   long long pad1;
 };
@@ -70,16 +73,16 @@ struct GridGeom {
 // Where a Block's boundary value of direction i goes when the fused
 // exchange writes it into the ghost layer of neighbour M (one entry per
 // Block and offset class d):
-//   kind 1 (M's main arrays):   main0 + i*Sf + z*Sz + y*Sx + x
-//   kind 2 (M's x-ghost planes): xg0 + k*P + z*Ry + y,  k = slot of i
-// with (x, y, z) the sender's local cell; the translation into M's frame and
-// the plane side are folded into main0 / xg0.  kind 0: no neighbour (wall).
+//   kind 1 (M's main arrays):    main0 + i*Sf + z*Sz + y*Sx + x
+//   kind 2 (M's x-ghost planes): xg0 + i*Sf + z*Ry + y
+// with (x, y, z) the sender's local cell; the translation into M's frame is
+// folded into main0 / xg0.  kind 0: no neighbour (wall).
 struct GhostTgt {
   long long main0;
   long long xg0;
   long long Sz;
   long long Sf;
-  int Sx, Ry, P, kind;
+  int Sx, Ry, kind, pad;
 };
 
 template <typename C>
@@ -97,6 +100,11 @@ struct Phys {
   C c9g[kQ];        // 9 w_i rho0 (e_i . g)
   C cfa[kQ];        // (1 - omega/2) 3 w_i rho0 (e_i . g)
   C corr[kQ][6];    // 6 w_i rho0 (e_i . u_w[face])
+  // FP64 copies for the mixed arithmetic of FP32 storage (velocity, odd part
+  // of the equilibrium and force, final update in FP64; even part in FP32)
+  double dinv_rho0, dhg[3], domega, domc;
+  double dc3w[kQ];
+  double dcfa[kQ];
 };
 
 struct SweepArgs {

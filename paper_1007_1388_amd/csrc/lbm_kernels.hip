@@ -22,8 +22,7 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ lattice
-// D3Q19 direction i -> e_i, opposite, and its slot among the five populations
-// that cross an x face (x-ghost planes).  Sec. 2.1.
+// D3Q19 direction i -> e_i and its opposite.  Sec. 2.1.
 __host__ __device__ constexpr int EXd(int i) {
   constexpr int t[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
   return t[i];
@@ -38,15 +37,6 @@ __host__ __device__ constexpr int EZd(int i) {
 }
 __host__ __device__ constexpr int OPPd(int i) {
   constexpr int t[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-  return t[i];
-}
-// slot of direction i in the x-lo ghost planes (e_x = +1) / x-hi planes (e_x = -1)
-__host__ __device__ constexpr int KLOd(int i) {
-  constexpr int t[kQ] = {-1, 0, -1, -1, -1, -1, -1, 1, -1, 2, -1, 3, -1, 4, -1, -1, -1, -1, -1};
-  return t[i];
-}
-__host__ __device__ constexpr int KHId(int i) {
-  constexpr int t[kQ] = {-1, -1, 0, -1, -1, -1, -1, -1, 1, -1, 2, -1, 3, -1, 4, -1, -1, -1, -1};
   return t[i];
 }
 // lattice weight times a factor, from |e_i|^2
@@ -72,7 +62,15 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-__device__ __forceinline__ uint16_t f32_to_f16(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+// float -> binary16, round to nearest even.  Written as the conversion
+// instruction itself so the compiler cannot merge it with the preceding FMA
+// into one mixed-precision operation (a single rounding where the other
+// kernel variants round twice).
+__device__ __forceinline__ uint16_t f32_to_f16(float f) {
+  uint32_t r;
+  asm("v_cvt_f16_f32 %0, %1" : "=v"(r) : "v"(f));
+  return (uint16_t)(r & 0xffffu);
+}
 
 template <int PREC, typename C>
 __device__ __forceinline__ C to_c(typename Stor<PREC>::T v) {
@@ -110,13 +108,16 @@ template <> struct Raw<4> { typedef uint32_t V; };
 template <> struct Raw<8> { typedef uint32_t V __attribute__((ext_vector_type(2))); };
 template <> struct Raw<16> { typedef uint32_t V __attribute__((ext_vector_type(4))); };
 
-// One value at a scalar base plus a 32-bit lane byte offset (a single
-// global instruction with the base in SGPRs).
+// One value at a scalar base plus a 32-bit lane byte offset (one global
+// instruction with the base in SGPRs).
 template <typename T, bool NT>
 __device__ __forceinline__ T ldo(const T* base, uint32_t boff) {
   return ld<T, NT>((const T*)((const char*)base + boff));
 }
-
+template <typename T, bool NT>
+__device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
+  st<T, NT>((T*)((char*)base + boff), v);
+}
 // VEC consecutive values at a scalar base plus a 32-bit lane byte offset.
 template <typename T, int VEC, bool NT>
 __device__ __forceinline__ void vld(const T* base, uint32_t boff, T (&out)[VEC]) {
@@ -142,16 +143,13 @@ __device__ __forceinline__ T sh_down(T v) {  // value of lane + 1
   else return __shfl_down(v, 1, 64);
 }
 
-template <typename A_, typename B_> constexpr bool kSameType = false;
-template <typename A_> constexpr bool kSameType<A_, A_> = true;
-
 // Flags of the wall faces that the sources of a lane's cells lie beyond.
 struct WallFlags {
   bool lox, hix, loy, hiy, loz, hiz;
 };
 
-// Wall link of direction i at element k of VEC: the source lies beyond a
-// wall face (x faces only concern the first / last element of the lane).
+// Wall link of direction i at element k of VEC: the source x - e_i lies
+// beyond a wall face (x faces only concern the lane's first / last element).
 template <int VEC>
 __device__ __forceinline__ bool wall_link(const WallFlags& w, int i, int k) {
   const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
@@ -166,7 +164,8 @@ __device__ __forceinline__ bool wall_link(const WallFlags& w, int i, int k) {
 }
 
 // 6 w_i rho0 (e_i . u_w) of the first moving face (order -x,+x,-y,+y,-z,+z)
-// that the source of a wall link lies beyond.
+// that the source of a wall link lies beyond (the half-way bounce-back rule
+// with wall velocity, Sec. 2.1).
 template <typename C, int VEC>
 __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, const WallFlags& w, int i, int k) {
   const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
@@ -183,15 +182,22 @@ __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, co
 // One wave updates a row segment: each lane owns VEC consecutive cells of a
 // row, xw lanes per row (the smallest power of two covering the row, at most
 // 64), 64/xw rows per wave, so the plane z and the first row y0w are uniform
-// and every stream is one aligned vector access at a scalar base plus the
-// lane's offset.  The x +- 1 neighbours come from the adjacent lane (lane
-// shuffle), from the next row segment, or from the x-ghost planes.  Per cell:
-// pull (Sec. 2.1, pull scheme); half-way bounce-back with wall velocity
-// (Sec. 2.1, bounce-back rule); moments; BGK collision with the shifted
-// incompressible equilibrium of Eq. (2) and the Guo force term, evaluated per
-// pair of opposite directions (the even part of feq and F is shared, the odd
-// part flips sign); aligned stores; with FUSED also the copy of boundary
-// values into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
+// and every stream is one access at a scalar base (SGPRs) plus a 32-bit lane
+// offset.
+//
+// Pull phase (branch-free, all 19 streams in flight): every population comes
+// from its source slot x - e_i -- inside the Block, from the ghost layer (the
+// neighbour Block's value), or from a bounce-back slot written by this cell in
+// the previous step (Sec. 2.1: pull scheme and half-way bounce-back).  With
+// one cell per lane the x-shifted source is a shifted load; with two, the
+// adjacent lane's value arrives by a lane shuffle.
+//
+// Update phase: moments, BGK collision with the shifted incompressible
+// equilibrium of Eq. (2) and the Guo force term, evaluated per pair of
+// opposite directions (even part of feq and F shared, odd part flips sign);
+// aligned stores; bounce-back writes f*_ibar + 6 w_i rho0 e_i.u_w into the
+// slot of every wall/obstacle link; with FUSED the boundary values also go
+// straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
@@ -205,14 +211,86 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   const int xl = lane - r * xw;
   const int x0 = seg * 64 * VEC + xl * VEC;
   const int y = y0w + r;
-  // Every lane of a live row takes part in the shuffles below; a lane only
-  // ever reads a neighbour lane of its own live row.
+  // Lanes of a live row all take part in the shuffles; a lane only reads a
+  // neighbour lane of its own live row.
   if (x0 >= a || y >= yend) return;
-  const bool first = xl == 0;
-  const bool last = (xl == xw - 1) || (x0 + VEC >= a);
 
+  const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx + seg * 64 * VEC;
+  const uint32_t lo = (uint32_t)(r * B.Sx + xl * VEC);
+  const uint32_t lob = lo * (uint32_t)sizeof(T);
+  const bool xg_lo = x0 == 0;              // first cell pulls e_x = +1 from the x-ghost plane
+  const bool xg_hi = x0 + VEC == a;         // last cell pulls e_x = -1 from the x-ghost plane
+  const bool first = xl == 0;
+  const bool last = (xl == xw - 1) || xg_hi;
+
+  // ---- pull phase: W[i][k] = stored value that cell k receives along e_i
+  T W[kQ][VEC];
+  T sv[kQ];           // VEC > 1: the vector element the adjacent lane needs
+  uint32_t eoff[kQ];  // VEC == 1: lane byte offset of the source slot from the source row
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
+    // source row of direction i, x-aligned
+    const long long row = rb + (long long)i * B.Sf - (long long)ez * B.Sz - (long long)ey * B.Sx;
+    // Scalar base one element before the row so that every lane offset is
+    // non-negative (x - 1 of a segment's first lane); the x-ghost slot of the
+    // lane's source row, relative to the same base:
+    const T* pr = src + (row - 1);
+    const long long dxg = B.xgo + (long long)(z + 1 - ez) * (B.Ry - B.Sz) +
+                          (long long)(y0w + 1 - ey) * (1 - B.Sx) - seg * 64 * VEC + 1;
+    const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
+    const uint32_t S1 = (uint32_t)sizeof(T);
+    if constexpr (VEC == 1) {
+      uint32_t off = lob + (uint32_t)((1 - ex) * (int)sizeof(T));
+      if (ex > 0) off = xg_lo ? xgb : off;
+      if (ex < 0) off = xg_hi ? xgb : off;
+      W[i][0] = ldo<T, NT>(pr, off);
+      eoff[i] = off;
+    } else {
+      T V[VEC];
+      vld<T, VEC, NT>(pr, lob + S1, V);
+      // the element just outside the vector: x-ghost slot, neighbouring
+      // segment, or (interior lanes, replaced by the shuffle) the lane's own
+      uint32_t off = lob + S1;
+      if (ex > 0) off = first ? (xg_lo ? xgb : lob) : lob + S1;
+      if (ex < 0) off = last ? (xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1) : lob + S1;
+      T e = V[0];
+      if (ex != 0) e = ldo<T, NT>(pr, off);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) W[i][k] = V[k];
+      if (ex > 0) {
+#pragma unroll
+        for (int k = VEC - 1; k > 0; --k) W[i][k] = V[k - 1];
+        W[i][0] = e;
+        sv[i] = V[VEC - 1];
+      } else if (ex < 0) {
+#pragma unroll
+        for (int k = 0; k < VEC - 1; ++k) W[i][k] = V[k + 1];
+        W[i][VEC - 1] = e;
+        sv[i] = V[0];
+      }
+    }
+  }
+  if constexpr (VEC > 1) {
+    // x +- 1 from the adjacent lane (all loads are in flight by now)
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      const int ex = EXd(i);
+      if (ex > 0) {
+        const T v = sh_up(sv[i]);
+        if (!first) W[i][0] = v;
+      }
+      if (ex < 0) {
+        const T v = sh_down(sv[i]);
+        if (!last) W[i][VEC - 1] = v;
+      }
+    }
+  }
+
+  // ---- update phase
   uint32_t m[VEC];
   bool solid[VEC];
+  bool anysolid = false;
 #pragma unroll
   for (int k = 0; k < VEC; ++k) {
     m[k] = 0;
@@ -224,11 +302,9 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     for (int k = 0; k < VEC; ++k) {
       m[k] = mp[k];
       solid[k] = (m[k] & kSolidBit) != 0;
+      anysolid = anysolid || solid[k];
     }
   }
-  const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx + seg * 64 * VEC;
-  const uint32_t lo = (uint32_t)(r * B.Sx + xl * VEC);
-  const uint32_t lob = lo * (uint32_t)sizeof(T);
   const int gx0 = B.org[0] + x0, gy = B.org[1] + y, gz = B.org[2] + z;
   WallFlags wf;
   wf.lox = A.geo.wall[0] && gx0 == 0;
@@ -240,96 +316,18 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   const bool moving = A.geo.moving[0] | A.geo.moving[1] | A.geo.moving[2] | A.geo.moving[3] | A.geo.moving[4] |
                       A.geo.moving[5];
 
-  // ---- pull: W[i][k] = stored value that cell k receives along e_i
-  T W[kQ][VEC];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
-    const T* pb = src + (rb + (long long)i * B.Sf - (long long)ez * B.Sz - (long long)ey * B.Sx);
-    if constexpr (VEC == 1) {
-      // one cell per lane: the x-shifted pull is a plain load at x - e_x
-      T v = ldo<T, NT>(pb - ex, lob);
-      if (ex > 0 && x0 == 0)
-        v = ld<T, NT>(src + B.xg + (long long)KLOd(i) * B.P + (long long)(z + 1 - ez) * B.Ry + (y + 1 - ey));
-      if (ex < 0 && x0 == a - 1)
-        v = ld<T, NT>(src + B.xg + (long long)(5 + KHId(i)) * B.P + (long long)(z + 1 - ez) * B.Ry +
-                      (y + 1 - ey));
-      W[i][0] = v;
-    } else {
-    T V[VEC];
-    vld<T, VEC, NT>(pb, lob, V);
-    if (ex == 0) {
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) W[i][k] = V[k];
-    } else if (ex > 0) {  // source x - 1
-#pragma unroll
-      for (int k = VEC - 1; k > 0; --k) W[i][k] = V[k - 1];
-      T e = sh_up(V[VEC - 1]);
-      if (first) {
-        if (x0 == 0)
-          e = ld<T, NT>(src + B.xg + (long long)KLOd(i) * B.P + (long long)(z + 1 - ez) * B.Ry + (y + 1 - ey));
-        else
-          e = ld<T, NT>(pb + (long long)lo - 1);
-      }
-      W[i][0] = e;
-    } else {  // source x + 1
-#pragma unroll
-      for (int k = 0; k < VEC - 1; ++k) W[i][k] = V[k + 1];
-      T e = sh_down(V[0]);
-      if (last) {
-        if (x0 + VEC == a)
-          e = ld<T, NT>(src + B.xg + (long long)(5 + KHId(i)) * B.P + (long long)(z + 1 - ez) * B.Ry +
-                        (y + 1 - ey));
-        else
-          e = ld<T, NT>(pb + (long long)lo + VEC);
-      }
-      W[i][VEC - 1] = e;
-    }
-    }
-    if (i > 0) {
-      // bounce-back links take the cell's own opposite population
-      bool any = false;
-      bool bbk[VEC];
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        bbk[k] = wall_link<VEC>(wf, i, k);
-        if constexpr (MASK) bbk[k] = bbk[k] || ((m[k] >> i) & 1u);
-        any = any || bbk[k];
-      }
-      if (any) {
-        T O[VEC];
-        vld<T, VEC, NT>(src + (rb + (long long)OPPd(i) * B.Sf), lob, O);
-#pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-          if (bbk[k]) {
-            W[i][k] = O[k];
-            // storage and arithmetic types agree: the moving-wall term is
-            // added here, exactly as in arithmetic precision
-            if constexpr (kSameType<T, C>)
-              if (moving && wall_link<VEC>(wf, i, k)) W[i][k] = O[k] + wall_corr<C, VEC>(A, ph, wf, i, k);
-          }
-        }
-      }
-    }
-  }
-
-  // value of population i at element k in arithmetic precision; with a
-  // narrower storage type the moving-wall term of a wall link is added here
-  auto fval = [&](int i, int k) -> C {
-    C v = to_c<PREC, C>(W[i][k]);
-    if constexpr (!kSameType<T, C>)
-      if (moving && i > 0 && wall_link<VEC>(wf, i, k)) v += wall_corr<C, VEC>(A, ph, wf, i, k);
-    return v;
-  };
-
-  // ---- moments (Sec. 2.1): drho = sum f~, rho0 u = sum e f~, plus half force
+  // moments (Sec. 2.1): drho = sum f~, rho0 u = sum e f~, plus half force.
+  // FP32 storage with FP32 arithmetic (HYB) keeps the velocity in FP64: the
+  // half-force shift g/2 is far below the rounding unit of u in FP32.
+  constexpr bool HYB = PREC == 1 && sizeof(C) == 4;
   C drho[VEC], ux[VEC], uy[VEC], uz[VEC], uu15[VEC], ug3[VEC];
+  double dux[VEC], duy[VEC], duz[VEC];
 #pragma unroll
   for (int k = 0; k < VEC; ++k) {
-    C d = fval(0, k), jx = (C)0, jy = (C)0, jz = (C)0;
+    C d = to_c<PREC, C>(W[0][k]), jx = (C)0, jy = (C)0, jz = (C)0;
 #pragma unroll
     for (int i = 1; i < kQ; i += 2) {  // (i, i+1) are opposite directions
-      const C fa = fval(i, k), fb = fval(i + 1, k);
+      const C fa = to_c<PREC, C>(W[i][k]), fb = to_c<PREC, C>(W[i + 1][k]);
       const C sp = fa + fb, dp = fa - fb;
       d += sp;
       if (EXd(i) > 0) jx += dp;
@@ -340,19 +338,85 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       if (EZd(i) < 0) jz -= dp;
     }
     drho[k] = d;
-    ux[k] = fma(jx, ph.inv_rho0, ph.hg[0]);
-    uy[k] = fma(jy, ph.inv_rho0, ph.hg[1]);
-    uz[k] = fma(jz, ph.inv_rho0, ph.hg[2]);
+    if constexpr (HYB) {
+      dux[k] = fma((double)jx, ph.dinv_rho0, ph.dhg[0]);
+      duy[k] = fma((double)jy, ph.dinv_rho0, ph.dhg[1]);
+      duz[k] = fma((double)jz, ph.dinv_rho0, ph.dhg[2]);
+      ux[k] = (C)dux[k];
+      uy[k] = (C)duy[k];
+      uz[k] = (C)duz[k];
+    } else {
+      ux[k] = fma(jx, ph.inv_rho0, ph.hg[0]);
+      uy[k] = fma(jy, ph.inv_rho0, ph.hg[1]);
+      uz[k] = fma(jz, ph.inv_rho0, ph.hg[2]);
+    }
     uu15[k] = (C)1.5 * fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
     ug3[k] = ph.rho0x3 * fma(ux[k], ph.g[0], fma(uy[k], ph.g[1], uz[k] * ph.g[2]));
   }
 
-  // ---- collision and stores
-  bool edge[VEC];
+  // stores of direction i for the fluid cells of the lane
+  auto store_dir = [&](int i, const T (&o)[VEC]) {
+    T* base = dst + (rb + (long long)i * B.Sf);
+    if (!anysolid) {
+      vst<T, VEC, NT>(base, lob, o);
+    } else {
 #pragma unroll
-  for (int k = 0; k < VEC; ++k)
-    edge[k] = FUSED && !solid[k] &&
-              ((x0 + k == 0) | (x0 + k == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
+      for (int k = 0; k < VEC; ++k)
+        if (!solid[k]) sto<T, NT>(base, lob + (uint32_t)(k * sizeof(T)), o[k]);
+    }
+  };
+  // bounce-back writes: cell k sends f*_q(x) to the slot (x - e_qbar, qbar)
+  // that it pulls along qbar next step when that source is a wall or solid
+  auto bounce = [&](int q, const T (&o)[VEC]) {
+    const int qb = OPPd(q);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      bool bb = wall_link<VEC>(wf, qb, k);
+      if constexpr (MASK) bb = (bb || ((m[k] >> qb) & 1u)) && !solid[k];
+      if (bb) {
+        const int exb = EXd(qb), eyb = EYd(qb), ezb = EZd(qb);
+        const long long row = rb + (long long)qb * B.Sf - (long long)ezb * B.Sz - (long long)eyb * B.Sx;
+        const uint32_t S1 = (uint32_t)sizeof(T);
+        uint32_t off;  // relative to row - 1, as in the pull phase
+        if constexpr (VEC == 1) {
+          off = eoff[qb];
+        } else {
+          const int j = k - exb;  // source element index relative to x0
+          const long long dxg = B.xgo + (long long)(z + 1 - ezb) * (B.Ry - B.Sz) +
+                                (long long)(y0w + 1 - eyb) * (1 - B.Sx) - seg * 64 * VEC + 1;
+          const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
+          if (j < 0) off = xg_lo ? xgb : lob;
+          else if (j >= VEC) off = xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1;
+          else off = lob + (uint32_t)(j + 1) * S1;
+        }
+        T v = o[k];
+        if (moving && wall_link<VEC>(wf, qb, k))
+          v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(A, ph, wf, qb, k));
+        sto<T, NT>(dst + (row - 1), off, v);
+      }
+    }
+  };
+  // fused exchange: boundary values of direction q into the neighbour's ghost
+  auto ghost = [&](int q, const T (&o)[VEC]) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int x = x0 + k;
+      const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
+      const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
+      const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
+      const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
+      if ((cx | cy | cz) != 0 && !solid[k]) {
+        const GhostTgt& G = A.ghost[bid * 27 + 13 + cx + 3 * cy + 9 * cz];
+        if (G.kind == 1)
+          dst[G.main0 + (long long)q * G.Sf + (long long)z * G.Sz + (long long)y * G.Sx + x] = o[k];
+        else if (G.kind == 2)
+          dst[G.xg0 + (long long)q * G.Sf + (long long)z * G.Ry + y] = o[k];
+      }
+    }
+  };
+  const bool edge = FUSED && ((x0 == 0) | (x0 + VEC - 1 == a - 1) | (y == 0) | (y == b - 1) | (z == 0) |
+                              (z == c - 1));
+
   {
     T o[VEC];
 #pragma unroll
@@ -360,10 +424,13 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       // rest: feq~_0 = w0 (drho + rho0 (-1.5 u.u)), F_0 = w0 rho0 (-3 u.g)
       const C feq = ph.w[0] * fma(ph.rho0, -uu15[k], drho[k]);
       const C F = -ph.w[0] * ug3[k];
-      const C post = fma(ph.omc, fval(0, k), fma(ph.omega, feq, ph.fcoef * F));
-      o[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(post);
+      const C even = fma(ph.omega, feq, ph.fcoef * F);
+      if constexpr (HYB)
+        o[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[0][k]), (double)even));
+      else
+        o[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[0][k]), even));
     }
-    vst<T, VEC, NT>(dst + rb, lob, o);
+    store_dir(0, o);
   }
 #pragma unroll
   for (int i = 1; i < kQ; i += 2) {
@@ -371,55 +438,50 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       C eu = (C)0;
-      if (EXd(i) > 0) eu += ux[k];
-      if (EXd(i) < 0) eu -= ux[k];
-      if (EYd(i) > 0) eu += uy[k];
-      if (EYd(i) < 0) eu -= uy[k];
-      if (EZd(i) > 0) eu += uz[k];
-      if (EZd(i) < 0) eu -= uz[k];
+      double deu = 0.0;
+      if constexpr (HYB) {
+        if (EXd(i) > 0) deu += dux[k];
+        if (EXd(i) < 0) deu -= dux[k];
+        if (EYd(i) > 0) deu += duy[k];
+        if (EYd(i) < 0) deu -= duy[k];
+        if (EZd(i) > 0) deu += duz[k];
+        if (EZd(i) < 0) deu -= duz[k];
+        eu = (C)deu;
+      } else {
+        if (EXd(i) > 0) eu += ux[k];
+        if (EXd(i) < 0) eu -= ux[k];
+        if (EYd(i) > 0) eu += uy[k];
+        if (EYd(i) < 0) eu -= uy[k];
+        if (EZd(i) > 0) eu += uz[k];
+        if (EZd(i) < 0) eu -= uz[k];
+      }
       // even part (shared by i and its opposite) and odd part (flips sign)
       const C sym = ph.w[i] * fma(ph.rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
-      const C asym = ph.c3w[i] * eu;
       const C Fs = fma(ph.c9g[i], eu, -ph.w[i] * ug3[k]);
       const C even = fma(ph.omega, sym, ph.fcoef * Fs);
-      const C odd = fma(ph.omega, asym, ph.cfa[i]);
-      o0[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(fma(ph.omc, fval(i, k), even + odd));
-      o1[k] = solid[k] ? from_c<PREC, C>((C)0) : from_c<PREC, C>(fma(ph.omc, fval(i + 1, k), even - odd));
-    }
-    vst<T, VEC, NT>(dst + (rb + (long long)i * B.Sf), lob, o0);
-    vst<T, VEC, NT>(dst + (rb + (long long)(i + 1) * B.Sf), lob, o1);
-    if constexpr (FUSED) {
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        if (!edge[k]) continue;
-        const int x = x0 + k;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int q = i + h;
-          const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
-          // x + e_q pulls f_q from x next step; outside this Block the value
-          // goes to the ghost layer of the Block that owns x + e_q
-          const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
-          const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
-          const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
-          if ((cx | cy | cz) != 0) {
-            const GhostTgt& G = A.ghost[bid * 27 + 13 + cx + 3 * cy + 9 * cz];
-            const T v = h == 0 ? o0[k] : o1[k];
-            if (G.kind == 1) {
-              dst[G.main0 + (long long)q * G.Sf + (long long)z * G.Sz + (long long)y * G.Sx + x] = v;
-            } else if (G.kind == 2) {
-              const int slot = qx > 0 ? KLOd(q) : KHId(q);
-              dst[G.xg0 + (long long)slot * G.P + (long long)z * G.Ry + y] = v;
-            }
-          }
-        }
+      if constexpr (HYB) {
+        const double odd = fma(ph.domega, ph.dc3w[i] * deu, ph.dcfa[i]);
+        const double ev = (double)even;
+        o0[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i][k]), ev + odd));
+        o1[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i + 1][k]), ev - odd));
+      } else {
+        const C odd = fma(ph.omega, ph.c3w[i] * eu, ph.cfa[i]);
+        o0[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i][k]), even + odd));
+        o1[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i + 1][k]), even - odd));
       }
+    }
+    store_dir(i, o0);
+    store_dir(i + 1, o1);
+    bounce(i, o0);
+    bounce(i + 1, o1);
+    if (edge) {
+      ghost(i, o0);
+      ghost(i + 1, o1);
     }
   }
 }
 
-// At least 4 (one cell per lane) or 3 (several cells per lane) waves per
-// SIMD: enough bytes in flight per compute unit without spilling.
+// At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
 template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
 k_sweep(const SweepArgs A, const Phys<C> ph) {
@@ -445,14 +507,20 @@ k_sweep(const SweepArgs A, const Phys<C> ph) {
 }
 
 // --------------------------------------------------------- ghost exchange
+__device__ __forceinline__ long long xg_off(const BlockDev& B, int i, int y, int z) {
+  return B.base + (long long)i * B.Sf + B.xgo + (long long)(z + 1) * B.Ry + (y + 1);
+}
+
 // Separate (unfused) exchange: after the sweep, copy the boundary values of
 // each neighbour Block straight into this Block's ghost layer (Sec. 4.3:
 // process-local communication copies from the sending to the receiving
 // Block).  One task = one (Block, neighbour offset, direction) triple.
+// Solid sources are skipped: those ghost slots hold bounce-back values.
 template <typename T>
 __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const BlockDev* __restrict__ blocks,
                                                   const NbrDev* __restrict__ nbr,
-                                                  const XchgTask* __restrict__ tasks, int ntasks) {
+                                                  const XchgTask* __restrict__ tasks, int ntasks,
+                                                  const uint32_t* __restrict__ mask) {
   for (int task = blockIdx.y; task < ntasks; task += gridDim.y) {
     const XchgTask t = tasks[task];
     const BlockDev M = blocks[t.dst];
@@ -470,14 +538,10 @@ __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const Bl
       if (gx + ex < 0 || gx + ex >= M.dim[0] || gy + ey < 0 || gy + ey >= M.dim[1] || gz + ez < 0 ||
           gz + ez >= M.dim[2])
         continue;
-      const long long so = main_off(N, i, gx + nb.tx, gy + nb.ty, gz + nb.tz);
-      long long o;
-      if (gx < 0)
-        o = M.xg + (long long)KLOd(i) * M.P + (long long)(gz + 1) * M.Ry + (gy + 1);
-      else if (gx >= M.dim[0])
-        o = M.xg + (long long)(5 + KHId(i)) * M.P + (long long)(gz + 1) * M.Ry + (gy + 1);
-      else
-        o = main_off(M, i, gx, gy, gz);
+      const int sx = gx + nb.tx, sy = gy + nb.ty, sz = gz + nb.tz;
+      if (mask && (mask[N.mask + ((long long)sz * N.dim[1] + sy) * N.dim[0] + sx] & kSolidBit)) continue;
+      const long long so = main_off(N, i, sx, sy, sz);
+      const long long o = (gx < 0 || gx >= M.dim[0]) ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz);
       grid[o] = grid[so];
     }
   }
@@ -539,6 +603,42 @@ __global__ void __launch_bounds__(256) k_linkmask(const uint8_t* __restrict__ so
       mask[B.mask + ((long long)z * B.dim[1] + y) * a + x] = m;
     }
   }
+}
+
+// Bounce-back slots of a state loaded from outside the sweep (rest state,
+// warm start, checkpoint): for every wall or obstacle link of a fluid cell x,
+// slot (x - e_i, i) = f_ibar(x) + 6 w_i rho0 e_i.u_w, rounded as the sweep
+// rounds it (arithmetic type C).
+template <int PREC, typename C>
+__global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const Phys<C> ph) {
+  using T = typename Stor<PREC>::T;
+  T* grid = (T*)grid_;
+  SweepArgs sa{};
+  sa.geo = A.geo;
+  const bool moving = A.geo.moving[0] | A.geo.moving[1] | A.geo.moving[2] | A.geo.moving[3] | A.geo.moving[4] |
+                      A.geo.moving[5];
+  for_cells(A, [&](const BlockDev& B, int x, int y, int z, bool solid) {
+    if (solid) return;
+    uint32_t m = 0;
+    if (A.has_mask) m = A.mask[B.mask + ((long long)z * B.dim[1] + y) * B.dim[0] + x];
+    const int gx = B.org[0] + x, gy = B.org[1] + y, gz = B.org[2] + z;
+    WallFlags wf;
+    wf.lox = A.geo.wall[0] && gx == 0;
+    wf.hix = A.geo.wall[0] && gx == A.geo.n[0] - 1;
+    wf.loy = A.geo.wall[1] && gy == 0;
+    wf.hiy = A.geo.wall[1] && gy == A.geo.n[1] - 1;
+    wf.loz = A.geo.wall[2] && gz == 0;
+    wf.hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
+    for (int i = 1; i < kQ; ++i) {
+      const bool bw = wall_link<1>(wf, i, 0);
+      if (!bw && !((m >> i) & 1u)) continue;
+      const int sx = x - EXd(i), sy = y - EYd(i), sz = z - EZd(i);
+      const long long o = (sx < 0 || sx >= B.dim[0]) ? xg_off(B, i, sy, sz) : main_off(B, i, sx, sy, sz);
+      T v = grid[main_off(B, OPPd(i), x, y, z)];
+      if (moving && bw) v = from_c<PREC, C>(to_c<PREC, C>(v) + wall_corr<C, 1>(sa, ph, wf, i, 0));
+      grid[o] = v;
+    }
+  });
 }
 
 // f~ = feq~(rho - rho0, u) of Eq. (2) in FP64 (warm start), 0 in solid cells.
@@ -727,31 +827,32 @@ static SweepFn pick3(bool mask, bool fused, bool nt) {
   return nt ? launch_sweep_t<PREC, C, false, false, true, VEC> : launch_sweep_t<PREC, C, false, false, false, VEC>;
 }
 
-// Cells per lane along x: 8 bytes of storage per lane and stream when every
-// Block's x extent allows it (vec_ok), else one.
-int sweep_vec(int prec, bool vec_ok) {
+// Cells per lane along x when every Block's x extent allows it (vec_ok),
+// else one: two for 16-bit storage (four bytes per lane and stream, like
+// FP32) and for FP32 storage with FP64 arithmetic.
+int sweep_vec(int prec, bool f64math, bool vec_ok) {
   if (!vec_ok) return 1;
-  return prec == 0 ? 1 : (prec == 1 ? 2 : 4);
+  return (prec >= 2 || (prec == 1 && f64math)) ? 2 : 1;
 }
 
 void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
-  const bool v = sweep_vec(prec, vec_ok) > 1;
+  const bool v = sweep_vec(prec, f64math, vec_ok) > 1;
   switch (prec) {
     case 0: fn = pick3<0, double, 1>(mask, fused, nt); break;
     case 1:
       if (f64math) fn = v ? pick3<1, double, 2>(mask, fused, nt) : pick3<1, double, 1>(mask, fused, nt);
-      else fn = v ? pick3<1, float, 2>(mask, fused, nt) : pick3<1, float, 1>(mask, fused, nt);
+      else fn = pick3<1, float, 1>(mask, fused, nt);
       break;
-    case 2: fn = v ? pick3<2, float, 4>(mask, fused, nt) : pick3<2, float, 1>(mask, fused, nt); break;
-    default: fn = v ? pick3<3, float, 4>(mask, fused, nt) : pick3<3, float, 1>(mask, fused, nt); break;
+    case 2: fn = v ? pick3<2, float, 2>(mask, fused, nt) : pick3<2, float, 1>(mask, fused, nt); break;
+    default: fn = v ? pick3<3, float, 2>(mask, fused, nt) : pick3<3, float, 1>(mask, fused, nt); break;
   }
   fn(a, pd, pf, grid, block, s);
 }
 
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
-                     int ntasks, int max_cells, hipStream_t s) {
+                     int ntasks, int max_cells, const uint32_t* mask, hipStream_t s) {
   if (ntasks <= 0) return;
   const int per = 256;
   int gx = (max_cells + per - 1) / per;
@@ -759,9 +860,23 @@ void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev*
   if (gx < 1) gx = 1;
   dim3 g(gx, ntasks < 65535 ? ntasks : 65535), b(per);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks); break;
-    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks); break;
-    default: hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks); break;
+    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks, mask); break;
+    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks, mask); break;
+    default: hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks, mask); break;
+  }
+}
+
+void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
+                   const Phys<float>& pf, hipStream_t s) {
+  dim3 g(a.nitems), b(256);
+  switch (prec) {
+    case 0: hipLaunchKernelGGL((k_bbfill<0, double>), g, b, 0, s, grid, a, pd); break;
+    case 1:
+      if (f64math) hipLaunchKernelGGL((k_bbfill<1, double>), g, b, 0, s, grid, a, pd);
+      else hipLaunchKernelGGL((k_bbfill<1, float>), g, b, 0, s, grid, a, pf);
+      break;
+    case 2: hipLaunchKernelGGL((k_bbfill<2, float>), g, b, 0, s, grid, a, pf); break;
+    default: hipLaunchKernelGGL((k_bbfill<3, float>), g, b, 0, s, grid, a, pf); break;
   }
 }
 

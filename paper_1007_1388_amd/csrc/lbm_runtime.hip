@@ -25,9 +25,11 @@
 namespace lbm {
 void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
-int sweep_vec(int prec, bool vec_ok);
+int sweep_vec(int prec, bool f64math, bool vec_ok);
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
-                     int ntasks, int max_cells, hipStream_t s);
+                     int ntasks, int max_cells, const uint32_t* mask, hipStream_t s);
+void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
+                   const Phys<float>& pf, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
 void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const double* rho, const double* u,
                     long long N, hipStream_t s);
@@ -325,9 +327,8 @@ std::vector<GhostTgt> build_ghost_table(const lbm_ctx* c) {
       g.Sf = M.Sf;
       g.Sx = M.Sx;
       g.Ry = M.Ry;
-      g.P = M.P;
       g.main0 = M.base + (long long)(n.tz + 1) * M.Sz + (long long)(n.ty + 1) * M.Sx + n.tx;
-      g.xg0 = M.xg + (cx < 0 ? 5LL * M.P : 0LL) + (long long)(n.tz + 1) * M.Ry + (n.ty + 1);
+      g.xg0 = M.base + M.xgo + (long long)(n.tz + 1) * M.Ry + (n.ty + 1);
       g.kind = cx == 0 ? 1 : 2;
     }
   return t;
@@ -335,7 +336,13 @@ std::vector<GhostTgt> build_ghost_table(const lbm_ctx* c) {
 
 void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s) {
   launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_tasks, (int)c->tasks_h.size(),
-                  c->xchg_max_cells, s);
+                  c->xchg_max_cells, c->has_mask ? c->d_mask : nullptr, s);
+}
+
+// Ghost layers and bounce-back slots of a state written from outside the sweep.
+void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
+  enqueue_exchange(c, g, s);
+  launch_bbfill(c->prec, c->f64math, c->grid[g], cell_args(c), c->phd, c->phf, s);
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
@@ -607,6 +614,22 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       for (int f = 0; f < 6; ++f) c->phf.corr[i][f] = (float)c->phd.corr[i][f];
     }
   }
+  {
+    // FP64 part of the mixed arithmetic (same values in both instantiations)
+    auto fill = [&](auto& ph) {
+      ph.dinv_rho0 = 1.0 / p->rho0;
+      ph.domega = omega;
+      ph.domc = 1.0 - omega;
+      for (int k = 0; k < 3; ++k) ph.dhg[k] = 0.5 * p->force[k];
+      for (int i = 0; i < kQ; ++i) {
+        const double eg = E3[i][0] * p->force[0] + E3[i][1] * p->force[1] + E3[i][2] * p->force[2];
+        ph.dc3w[i] = 3.0 * weight(i) * p->rho0;
+        ph.dcfa[i] = (1.0 - 0.5 * omega) * 3.0 * weight(i) * p->rho0 * eg;
+      }
+    };
+    fill(c->phd);
+    fill(c->phf);
+  }
 
   // per-Block layout (see lbm_internal.h)
   const long long align = 128 / c->sbytes;  // elements per 128-byte line
@@ -622,18 +645,18 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     B.Sx = (int)roundup(B.dim[0], align);
     B.Ry = B.dim[1] + 2;
     B.Sz = (long long)B.Sx * (B.dim[1] + 2);
-    const long long fmin = B.Sz * (B.dim[2] + 2);
+    // array (with y/z ghost layer), one spare row, then its x-ghost plane
+    B.xgo = B.Sz * (B.dim[2] + 2) + B.Sx;
+    const long long fmin = B.xgo + (long long)B.Ry * (B.dim[2] + 2);
     // stagger the 19 streams so they do not start on the same HBM channel
     B.Sf = roundup(fmin, 4096 / c->sbytes) + 768 / c->sbytes;
-    B.P = (int)roundup((long long)(B.dim[1] + 2) * (B.dim[2] + 2), 256 / c->sbytes);
     B.base = off;
-    B.xg = off + (long long)kQ * B.Sf;
-    off = roundup(B.xg + 10LL * B.P, 4096 / c->sbytes);
+    off = roundup(off + (long long)kQ * B.Sf, 4096 / c->sbytes);
     B.mask = -1;
   }
   c->grid_elems = (size_t)off;
   {
-    const int vw = sweep_vec(c->prec, true);
+    const int vw = sweep_vec(c->prec, c->f64math, true);
     c->vec_ok = true;
     for (const auto& B : c->bh)
       if (B.dim[0] % vw) c->vec_ok = false;
@@ -701,7 +724,10 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
                                         hipMemcpyHostToDevice) != hipSuccess))
     return bail(LBM_EDEVICE, "upload of block tables failed");
   if (upload_items(c) != LBM_OK) return bail(LBM_ENOMEM, "item list upload failed");
-  if (zero_grids(c) != LBM_OK || hipStreamSynchronize(c->stream) != hipSuccess)
+  if (zero_grids(c) != LBM_OK) return bail(LBM_EDEVICE, "grid initialisation failed");
+  // rest state: bounce-back slots of moving walls carry the wall term
+  launch_bbfill(c->prec, c->f64math, c->grid[0], cell_args(c), c->phd, c->phf, c->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(LBM_EDEVICE, "grid initialisation failed");
   *out = c;
   return LBM_OK;
@@ -745,6 +771,8 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   c->n_fluid = c->n_cells - nsolid;
   lbm_status s = zero_grids(c);
   if (s != LBM_OK) return s;
+  launch_bbfill(c->prec, c->f64math, c->grid[0], cell_args(c), c->phd, c->phf, c->stream);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cur = 0;
   c->steps = 0;
@@ -760,7 +788,7 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
   HIPCHK(hipMemcpyAsync(d, rho, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(d + N, u, 3 * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
   launch_init_eq(c->prec, c->grid[c->cur], cell_args(c), c->p.rho0, d, d + N, (long long)N, c->stream);
-  enqueue_exchange(c, c->cur, c->stream);
+  enqueue_fill(c, c->cur, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 0;
@@ -839,7 +867,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64) {
   if (s != LBM_OK) return s;
   HIPCHK(hipMemcpyAsync(c->d_stage, f, bytes, hipMemcpyHostToDevice, c->stream));
   launch_set_state(c->prec, as_fp64 != 0, c->grid[c->cur], cell_args(c), c->d_stage, (long long)N, c->stream);
-  enqueue_exchange(c, c->cur, c->stream);
+  enqueue_fill(c, c->cur, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 1;

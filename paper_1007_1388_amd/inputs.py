@@ -22,27 +22,48 @@ def porous_spheres(dims, target_fraction=0.10, radius=(3, 8), seed=0,
     dims = (nx, ny, nz); returns uint8 [nz, ny, nx], 1 = solid.  Centres are
     uniform in the domain, radii are integers uniform in [radius[0],
     radius[1]]; a cell is solid when its centre lies within the radius of a
-    sphere, taking periodic images on the axes flagged ``periodic``.
+    sphere, taking periodic images on the axes flagged ``periodic``.  Each
+    sphere only touches its bounding box.
     """
     nx, ny, nz = (int(d) for d in dims)
+    n = [nx, ny, nz]
     rng = np.random.default_rng(seed)
     solid = np.zeros((nz, ny, nx), dtype=bool)
-    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    n = [nx, ny, nz]
     target = float(target_fraction) * solid.size
     if target <= 0:
         return solid.astype(np.uint8)
-    for _ in range(100000):
+    count = 0
+    for _ in range(1_000_000):
         c = rng.uniform(0, 1, 3) * np.array(n)
         r = int(rng.integers(radius[0], radius[1] + 1))
-        d2 = np.zeros(solid.shape)
-        for axis, coord in enumerate((xx, yy, zz)):
-            diff = np.abs(coord - c[axis])
+        idx, d2 = [], []
+        for axis in range(3):
+            lo = int(np.floor(c[axis] - r)) - 1
+            hi = int(np.ceil(c[axis] + r)) + 2
+            cells = np.arange(lo, hi)
             if periodic[axis]:
-                diff = np.minimum(diff, n[axis] - diff)
-            d2 = d2 + diff * diff
-        solid |= d2 <= r * r
-        if solid.sum() >= target:
+                cells = cells[(cells - lo) < n[axis]] if hi - lo > n[axis] else cells
+                wrapped = cells % n[axis]
+                # distance to the nearest periodic image of the centre
+                dd = np.abs(wrapped - c[axis])
+                diff = np.minimum(dd, n[axis] - dd)
+                order = np.unique(wrapped, return_index=True)[1]
+                wrapped, diff = wrapped[order], diff[order]
+                idx.append(wrapped)
+                d2.append(diff * diff)
+            else:
+                keep = (cells >= 0) & (cells < n[axis])
+                cells = cells[keep]
+                idx.append(cells)
+                d2.append((cells - c[axis]) ** 2)
+        if any(len(v) == 0 for v in idx):
+            continue
+        ball = (d2[2][:, None, None] + d2[1][None, :, None] + d2[0][None, None, :]) <= r * r
+        box = np.ix_(idx[2], idx[1], idx[0])
+        before = solid[box]
+        count += int((ball & ~before).sum())
+        solid[box] = before | ball
+        if count >= target:
             break
     return solid.astype(np.uint8)
 

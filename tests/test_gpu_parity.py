@@ -96,6 +96,20 @@ def test_channel_f32_storage(fp64_math):
     check_vs_oracle(lat, o, TOL["f32"])
 
 
+@pytest.mark.parametrize("precision,tol", [("f16s", 1e-2), ("bf16s", 5e-2)])
+@pytest.mark.parametrize("dims", [(24, 12, 10), (13, 12, 10)])
+def test_shifted_half_storage_tracks_oracle(precision, tol, dims):
+    # Storage rounding of 2^-11 (FP16) / 2^-8 (BF16) of |f~| ~ w 3|u| per step
+    # accumulates to ~1e-3 / ~1e-2 relative velocity error over 100 steps.
+    case = cavity(dims=dims, lid=(0.05, 0.0, 0.0))
+    case["solid"] = inputs.porous_spheres(dims, target_fraction=0.05, radius=(1, 2), seed=9,
+                                          periodic=(False, False, False))
+    lat = run_gpu(case, 100, precision=precision)
+    o = run_oracle(case, 100)
+    err = field_errors(*lat.macroscopic(), *o.macroscopic())
+    assert err["u_inf"] < tol, err
+
+
 def test_porous_multiblock_f64_matches_oracle():
     dims = (40, 24, 20)
     solid = inputs.porous_spheres(dims, target_fraction=0.15, radius=(2, 4), seed=5)

@@ -149,8 +149,9 @@ def test_mse_and_adam():
 
 
 def _ref_unet(net, x):
-    """FP64 forward of the same network with oracle.conv, on BF16-rounded
-    weights (activations kept in FP64); returns all intermediate tensors."""
+    """FP64 forward of the same network with oracle.conv, rounding every
+    stored activation to BF16 where the GPU stores one; returns all
+    intermediate tensors."""
     W = {}
     for name in ("e0a e0b dn0 e1a e1b dn1 e2a e2b dn2 e3a e3b up2 d2a d2b up1 d1a d1b up0 d0a d0b head").split():
         l = getattr(net, name)
@@ -159,7 +160,7 @@ def _ref_unet(net, x):
 
     def C(name, t):
         w, b, k, s, r = W[name]
-        return conv.conv3d(t, w, b, k, s, r)
+        return bf(conv.conv3d(t, w, b, k, s, r))
 
     T = {}
     T["a0"] = C("e0a", x)
@@ -190,44 +191,62 @@ def _ref_unet(net, x):
 
 
 def _ref_grads(W, T, x, dpred):
-    """FP64 backward through the same graph (adjoints from oracle.conv)."""
+    """FP64 backward through the same graph (adjoints from oracle.conv); a data
+    gradient is masked by ReLU'(input) and rounded to BF16 where the GPU
+    stores it, exactly in the GPU's order of accumulation."""
     G = {}
 
-    def back(name, xin, dout_post, out_post):
+    def wgrad(name, xin, dpre):
         w, b, k, s, r = W[name]
-        dpre = dout_post * (out_post > 0) if r else dout_post
-        dw, db = conv.conv3d_bwd_weight(xin, dpre, k, s)
-        G[name] = (dw, db)
-        return conv.conv3d_bwd_data(dpre, w, xin.shape, k, s)
+        G[name] = conv.conv3d_bwd_weight(xin, dpre, k, s)
 
-    g = back("head", T["d0o"], dpred, T["pred"])
-    g = back("d0b", T["d0"], g, T["d0o"])
-    gc0 = back("d0a", T["c0"], g, T["d0"])
-    c0 = T["s0"].shape[-1]
-    up0_out = T["c0"][..., :c0]
-    g = back("up0", T["u0"], gc0[..., :c0], up0_out)
-    g = conv.upsample2_bwd(g)
-    g = back("d1b", T["d1"], g, T["d1o"])
-    gc1 = back("d1a", T["c1"], g, T["d1"])
-    c1 = T["s1"].shape[-1]
-    g = back("up1", T["u1"], gc1[..., :c1], T["c1"][..., :c1])
-    g = conv.upsample2_bwd(g)
-    g = back("d2b", T["d2"], g, T["d2o"])
-    gc2 = back("d2a", T["c2"], g, T["d2"])
-    c2 = T["s2"].shape[-1]
-    g = back("up2", T["u2"], gc2[..., :c2], T["c2"][..., :c2])
-    g = conv.upsample2_bwd(g)
-    g = back("e3b", T["a3"], g, T["b3"])
-    g = back("e3a", T["l3"], g, T["a3"])
-    g = back("dn2", T["s2"], g, T["l3"]) + gc2[..., c2:]
-    g = back("e2b", T["a2"], g, T["s2"])
-    g = back("e2a", T["l2"], g, T["a2"])
-    g = back("dn1", T["s1"], g, T["l2"]) + gc1[..., c1:]
-    g = back("e1b", T["a1"], g, T["s1"])
-    g = back("e1a", T["l1"], g, T["a1"])
-    g = back("dn0", T["s0"], g, T["l1"]) + gc0[..., c0:]
-    g = back("e0b", T["a0"], g, T["s0"])
-    back("e0a", x, g, T["a0"])
+    def dgrad(name, xin, dpre, act=True):
+        w, b, k, s, r = W[name]
+        g = conv.conv3d_bwd_data(dpre, w, xin.shape, k, s)
+        return g * (xin > 0) if act else g
+
+    c0, c1, c2 = T["s0"].shape[-1], T["s1"].shape[-1], T["s2"].shape[-1]
+    wgrad("head", T["d0o"], dpred)
+    g = bf(dgrad("head", T["d0o"], dpred))
+    wgrad("d0b", T["d0"], g)
+    g = bf(dgrad("d0b", T["d0"], g))
+    wgrad("d0a", T["c0"], g)
+    gc0 = bf(dgrad("d0a", T["c0"], g))
+    wgrad("up0", T["u0"], gc0[..., :c0])
+    g = bf(conv.upsample2_bwd(bf(dgrad("up0", T["u0"], gc0[..., :c0]))))
+    wgrad("d1b", T["d1"], g)
+    g = bf(dgrad("d1b", T["d1"], g))
+    wgrad("d1a", T["c1"], g)
+    gc1 = bf(dgrad("d1a", T["c1"], g))
+    wgrad("up1", T["u1"], gc1[..., :c1])
+    g = bf(conv.upsample2_bwd(bf(dgrad("up1", T["u1"], gc1[..., :c1]))))
+    wgrad("d2b", T["d2"], g)
+    g = bf(dgrad("d2b", T["d2"], g))
+    wgrad("d2a", T["c2"], g)
+    gc2 = bf(dgrad("d2a", T["c2"], g))
+    wgrad("up2", T["u2"], gc2[..., :c2])
+    g = bf(conv.upsample2_bwd(bf(dgrad("up2", T["u2"], gc2[..., :c2]))))
+    wgrad("e3b", T["a3"], g)
+    g = bf(dgrad("e3b", T["a3"], g))
+    wgrad("e3a", T["l3"], g)
+    g = bf(dgrad("e3a", T["l3"], g))
+    wgrad("dn2", T["s2"], g)
+    g = bf(gc2[..., c2:] + dgrad("dn2", T["s2"], g))
+    wgrad("e2b", T["a2"], g)
+    g = bf(dgrad("e2b", T["a2"], g))
+    wgrad("e2a", T["l2"], g)
+    g = bf(dgrad("e2a", T["l2"], g))
+    wgrad("dn1", T["s1"], g)
+    g = bf(gc1[..., c1:] + dgrad("dn1", T["s1"], g))
+    wgrad("e1b", T["a1"], g)
+    g = bf(dgrad("e1b", T["a1"], g))
+    wgrad("e1a", T["l1"], g)
+    g = bf(dgrad("e1a", T["l1"], g))
+    wgrad("dn0", T["s0"], g)
+    g = bf(gc0[..., c0:] + dgrad("dn0", T["s0"], g))
+    wgrad("e0b", T["a0"], g)
+    g = bf(dgrad("e0b", T["a0"], g))
+    wgrad("e0a", x, g)
     return G
 
 
@@ -238,21 +257,33 @@ def test_whole_network_gradients_match_fp64_reference():
     x = np.zeros((1, 16, 8, 8, 8))
     x[..., :3] = rng.standard_normal((1, 16, 8, 8, 3))
     x = bf(x)
-    net.x.buf.copy_(S.from_numpy(x).buf)
+    X = S.from_numpy(x)
+    net.x.buf.copy_(X.buf)
     pred = net.forward()
     W, T = _ref_unet(net, x)
-    # BF16 activations on the GPU vs FP64 ones in the reference: a few 1e-2
-    assert rel(pred.to_numpy(), T["pred"]) < 1e-1, rel(pred.to_numpy(), T["pred"])
+    # same BF16 storage points: differences come from FP32 vs FP64 sums and
+    # the occasional activation rounded across a BF16 boundary
+    assert rel(pred.to_numpy(), T["pred"]) < 2e-2, rel(pred.to_numpy(), T["pred"])
     dpred = np.zeros_like(T["pred"])
     dpred[..., :4] = bf(rng.standard_normal(dpred[..., :4].shape))
+    D = S.from_numpy(dpred)
     net.zero_grad()
-    net.backward(S.from_numpy(dpred))
+    net.backward(D)
     G = _ref_grads(W, T, x, dpred)
-    worst = 0.0
     for name, (dw, db) in G.items():
         l = getattr(net, name)
         gw = l.gw.cpu().numpy()[:, :l.taps * l.cin].reshape(dw.shape)
         cos = (gw * dw).sum() / (np.linalg.norm(gw) * np.linalg.norm(dw) + 1e-300)
-        worst = max(worst, rel(gw, dw))
-        assert cos > 0.98, (name, cos)
-    assert worst < 0.2, worst
+        frob = np.linalg.norm(gw - dw) / (np.linalg.norm(dw) + 1e-300)
+        # each stored BF16 activation or gradient may round to the other
+        # neighbour when the FP32 and FP64 sums straddle a BF16 boundary; over
+        # eight stored layers that drift reaches cos ~0.99.  Wiring mistakes
+        # (a dropped ReLU mask, a wrong concat slice or transposed taps) put
+        # cos well below 0.9.
+        assert cos > 0.98 and frob < 0.2, (name, cos, frob)
+        # bias gradients are sums over all voxels with heavy cancellation, so
+        # BF16-level differences of the incoming gradient are amplified:
+        # compare directions
+        gb = l.gb.cpu().numpy()
+        cb = (gb * db).sum() / (np.linalg.norm(gb) * np.linalg.norm(db) + 1e-300)
+        assert cb > 0.98, (name, cb)

@@ -136,6 +136,14 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u);
  * the ghost exchange) on the context stream.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
+/* Advances n steps (1 <= n <= 100000) exactly as lbm_step does, launched one
+ * by one (no graphs), with a HIP event pair around every sweep launch and
+ * every separate ghost-exchange launch on params.stream; returns the mean
+ * duration of one sweep launch and of one exchange launch (0 when the
+ * exchange is fused into the sweep), in milliseconds: the per-kernel
+ * durations that bandwidth accounting divides by.  Synchronises. */
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms);
+
 /* Density and velocity used by the most recent collision (before any step:
  * the initial field), FP64: rho[N], u[3*N]; solid cells give rho0 and 0.
  * dst_is_device = 1: rho/u are device pointers.  Synchronises. */

@@ -201,7 +201,7 @@ __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, co
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
-                                          int z, int y0w, int seg, int yend, int xw) {
+                                          int z, int y0w, int seg, int yend, int xw, const GhostTgt* gts) {
   using T = typename Stor<PREC>::T;
   const T* __restrict__ src = (const T*)A.src;
   T* __restrict__ dst = (T*)A.dst;
@@ -225,8 +225,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 
   // ---- pull phase: W[i][k] = stored value that cell k receives along e_i
   T W[kQ][VEC];
-  T sv[kQ];           // VEC > 1: the vector element the adjacent lane needs
-  uint32_t eoff[kQ];  // VEC == 1: lane byte offset of the source slot from the source row
+  T sv[kQ];  // VEC > 1: the vector element the adjacent lane needs
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
@@ -245,7 +244,6 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       if (ex > 0) off = xg_lo ? xgb : off;
       if (ex < 0) off = xg_hi ? xgb : off;
       W[i][0] = ldo<T, NT>(pr, off);
-      eoff[i] = off;
     } else {
       T V[VEC];
       vld<T, VEC, NT>(pr, lob + S1, V);
@@ -377,18 +375,16 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
         const int exb = EXd(qb), eyb = EYd(qb), ezb = EZd(qb);
         const long long row = rb + (long long)qb * B.Sf - (long long)ezb * B.Sz - (long long)eyb * B.Sx;
         const uint32_t S1 = (uint32_t)sizeof(T);
-        uint32_t off;  // relative to row - 1, as in the pull phase
-        if constexpr (VEC == 1) {
-          off = eoff[qb];
-        } else {
-          const int j = k - exb;  // source element index relative to x0
-          const long long dxg = B.xgo + (long long)(z + 1 - ezb) * (B.Ry - B.Sz) +
-                                (long long)(y0w + 1 - eyb) * (1 - B.Sx) - seg * 64 * VEC + 1;
-          const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
-          if (j < 0) off = xg_lo ? xgb : lob;
-          else if (j >= VEC) off = xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1;
-          else off = lob + (uint32_t)(j + 1) * S1;
-        }
+        // the pull phase's source slot, relative to row - 1 (recomputed here
+        // rather than held in registers through the collision)
+        uint32_t off;
+        const int j = k - exb;  // source element index relative to x0
+        const long long dxg = B.xgo + (long long)(z + 1 - ezb) * (B.Ry - B.Sz) +
+                              (long long)(y0w + 1 - eyb) * (1 - B.Sx) - seg * 64 * VEC + 1;
+        const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
+        if (j < 0) off = xg_lo ? xgb : lob;
+        else if (j >= VEC) off = xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1;
+        else off = lob + (uint32_t)(j + 1) * S1;
         T v = o[k];
         if (moving && wall_link<VEC>(wf, qb, k))
           v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(A, ph, wf, qb, k));
@@ -396,26 +392,45 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       }
     }
   };
-  // fused exchange: boundary values of direction q into the neighbour's ghost
-  auto ghost = [&](int q, const T (&o)[VEC]) {
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const int x = x0 + k;
-      const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
-      const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
-      const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
-      const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
-      if ((cx | cy | cz) != 0 && !solid[k]) {
-        const GhostTgt& G = A.ghost[bid * 27 + 13 + cx + 3 * cy + 9 * cz];
-        if (G.kind == 1)
-          dst[G.main0 + (long long)q * G.Sf + (long long)z * G.Sz + (long long)y * G.Sx + x] = o[k];
-        else if (G.kind == 2)
-          dst[G.xg0 + (long long)q * G.Sf + (long long)z * G.Ry + y] = o[k];
-      }
-    }
+  // fused exchange, generic case: neighbour (cx, cy, cz) of cell x0 + k
+  // receives direction q when q leaves the Block through that face/edge/corner
+  auto nbr_of = [&](int q, int k) {
+    const int x = x0 + k;
+    const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
+    const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
+    const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
+    const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
+    return (cx | cy | cz) != 0 && !solid[k] ? 13 + cx + 3 * cy + 9 * cz : 13;
   };
-  const bool edge = FUSED && ((x0 == 0) | (x0 + VEC - 1 == a - 1) | (y == 0) | (y == b - 1) | (z == 0) |
-                              (z == c - 1));
+  // Rows of this wave (y0w .. ylast, z fixed) off the y and z faces of the
+  // Block only send from their first and last cell, to the two x-face
+  // neighbours: their table entries are wave-uniform and read once.  Waves
+  // with a row on a y or z face take the generic per-lane path.
+  const int ylast = min(y0w + 64 / xw, yend) - 1;
+  const bool yz_face = (z == 0) | (z == c - 1) | (y0w == 0) | (ylast >= b - 1);
+  const bool edge = FUSED && yz_face &&
+                    ((x0 == 0) | (x0 + VEC - 1 == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
+  // x-ghost slot of row y for direction q: base + q * Sf (wave-uniform) plus
+  // the lane's row offset within the wave
+  long long xm0 = 0, xmf = 0, xp0 = 0, xpf = 0;
+  bool xm_on = false, xp_on = false;
+  if (FUSED && !yz_face) {
+    const GhostTgt& Gm = A.ghost[bid * 27 + 12];
+    const GhostTgt& Gp = A.ghost[bid * 27 + 14];
+    xm_on = Gm.kind != 0;
+    xp_on = Gp.kind != 0;
+    xm0 = Gm.xg0 + (long long)z * Gm.Ry + y0w;
+    xp0 = Gp.xg0 + (long long)z * Gp.Ry + y0w;
+    xmf = Gm.Sf;
+    xpf = Gp.Sf;
+  }
+  const uint32_t roff = (uint32_t)(r * (int)sizeof(T));
+  const bool send_lo = xm_on && x0 == 0 && !solid[0];
+  const bool send_hi = xp_on && x0 + VEC - 1 == a - 1 && !solid[VEC - 1];
+  auto xface = [&](int q, const T (&o)[VEC]) {
+    if (EXd(q) < 0 && send_lo) sto<T, false>(dst + (xm0 + (long long)q * xmf), roff, o[0]);
+    if (EXd(q) > 0 && send_hi) sto<T, false>(dst + (xp0 + (long long)q * xpf), roff, o[VEC - 1]);
+  };
 
   {
     T o[VEC];
@@ -474,9 +489,38 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     store_dir(i + 1, o1);
     bounce(i, o0);
     bounce(i + 1, o1);
+    if (FUSED && !yz_face) {
+      xface(i, o0);
+      xface(i + 1, o1);
+    }
+  }
+  if constexpr (FUSED) {
+    // Waves with a row on a y or z face: the lane re-reads the values it has
+    // just stored (same-address order within a lane), all loads first, then
+    // sends them to the neighbours' ghost layers through the Block's target
+    // table staged in LDS.
     if (edge) {
-      ghost(i, o0);
-      ghost(i + 1, o1);
+      T v[kQ][VEC];
+#pragma unroll
+      for (int q = 1; q < kQ; ++q)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+          if (nbr_of(q, k) != 13)
+            v[q][k] = ldo<T, false>(dst + (rb + (long long)q * B.Sf), lob + (uint32_t)(k * sizeof(T)));
+#pragma unroll
+      for (int q = 1; q < kQ; ++q)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          const int d = nbr_of(q, k);
+          if (d != 13) {
+            const GhostTgt& G = gts[d];
+            const int x = x0 + k;
+            if (G.kind == 1)
+              dst[G.main0 + (long long)q * G.Sf + (long long)z * G.Sz + (long long)y * G.Sx + x] = v[q][k];
+            else if (G.kind == 2)
+              dst[G.xg0 + (long long)q * G.Sf + (long long)z * G.Ry + y] = v[q][k];
+          }
+        }
     }
   }
 }
@@ -487,8 +531,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 
 k_sweep(const SweepArgs A, const Phys<C> ph) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
+  // ghost targets of the current item's Block (fused exchange)
+  __shared__ GhostTgt gts[FUSED ? 27 : 1];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const ItemDev item = A.items[it];
+    if constexpr (FUSED) {
+      __syncthreads();  // the previous item's readers are done
+      if (threadIdx.x < 27) gts[threadIdx.x] = A.ghost[item.block * 27 + threadIdx.x];
+      __syncthreads();
+    }
     const BlockDev B = A.blocks[item.block];
     const int a = B.dim[0];
     const int lanes = (a + VEC - 1) / VEC;  // lanes per row
@@ -501,7 +552,7 @@ k_sweep(const SweepArgs A, const Phys<C> ph) {
     const int yend = item.y0 + item.nrows;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FUSED, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw);
+      sweep_row<PREC, C, MASK, FUSED, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw, gts);
     }
   }
 }

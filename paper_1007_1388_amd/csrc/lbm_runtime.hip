@@ -345,7 +345,7 @@ void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
   launch_bbfill(c->prec, c->f64math, c->grid[g], cell_args(c), c->phd, c->phf, s);
 }
 
-void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
+void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   const SweepArgs a = sweep_args(c, from);
   const int nitems = (int)c->items_h.size();
   int grid = nitems;
@@ -353,6 +353,10 @@ void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
   if (grid < 1) grid = 1;
   launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0,
                c->vec_ok, a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+}
+
+void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
+  enqueue_sweep(c, from, s);
   if (!c->sched.fused_exchange) enqueue_exchange(c, 1 - from, s);
 }
 
@@ -799,6 +803,48 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   return run_steps(c, n);
+}
+
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms) {
+  if (!c || !sweep_ms || !exchange_ms) return fail(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > 100000) return fail(LBM_EINVAL, "step count must be in [1, 100000]");
+  const bool ex = !c->sched.fused_exchange;
+  const size_t ne = (size_t)n * (ex ? 3 : 2);
+  std::vector<hipEvent_t> ev(ne, nullptr);
+  lbm_status st = LBM_OK;
+  for (size_t k = 0; k < ne && st == LBM_OK; ++k)
+    if (hipEventCreate(&ev[k]) != hipSuccess) st = fail(LBM_EDEVICE, "hipEventCreate failed");
+  double ts = 0.0, te = 0.0;
+  if (st == LBM_OK) {
+    size_t k = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      (void)hipEventRecord(ev[k++], c->stream);
+      enqueue_sweep(c, c->cur, c->stream);
+      (void)hipEventRecord(ev[k++], c->stream);
+      if (ex) {
+        enqueue_exchange(c, 1 - c->cur, c->stream);
+        (void)hipEventRecord(ev[k++], c->stream);
+      }
+      c->cur = 1 - c->cur;
+      c->steps += 1;
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+      st = fail(LBM_EDEVICE, "timed steps failed");
+    for (size_t b = 0; st == LBM_OK && b < ne; b += ex ? 3 : 2) {
+      float t0 = 0.f, t1 = 0.f;
+      if (hipEventElapsedTime(&t0, ev[b], ev[b + 1]) != hipSuccess ||
+          (ex && hipEventElapsedTime(&t1, ev[b + 1], ev[b + 2]) != hipSuccess))
+        st = fail(LBM_EDEVICE, "hipEventElapsedTime failed");
+      ts += t0;
+      te += t1;
+    }
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st != LBM_OK) return st;
+  *sweep_ms = ts / (double)n;
+  *exchange_ms = ex ? te / (double)n : 0.0;
+  return LBM_OK;
 }
 
 lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_device) {

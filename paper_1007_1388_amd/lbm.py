@@ -72,7 +72,7 @@ class lbm_info(ctypes.Structure):
 
 # The exported symbols of include/lbm.h, in declaration order.
 SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step",
-           "lbm_macroscopic", "lbm_residual", "lbm_sums", "lbm_get_state", "lbm_set_state",
+           "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_sums", "lbm_get_state", "lbm_set_state",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_autotune", "lbm_info_get", "lbm_destroy",
            "lbm_strerror", "lbm_last_error", "lbm_bw_probe"]
 
@@ -100,6 +100,7 @@ def load(path=LIB_PATH):
         "lbm_set_geometry": [P, P],
         "lbm_set_equilibrium": [P, dp, dp],
         "lbm_step": [P, ctypes.c_int64],
+        "lbm_step_timed": [P, ctypes.c_int64, dp, dp],
         "lbm_macroscopic": [P, P, P, ctypes.c_int32],
         "lbm_residual": [P, dp],
         "lbm_sums": [P, dp, dp],
@@ -164,6 +165,14 @@ def lbm_set_equilibrium(ctx, rho, u):
 
 def lbm_step(ctx, n):
     _check(load().lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_step_timed(ctx, n):
+    """n steps with per-launch HIP events: (mean sweep ms, mean exchange ms)."""
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(load().lbm_step_timed(ctx, int(n), ctypes.byref(a), ctypes.byref(b)), "lbm_step_timed")
+    return a.value, b.value
 
 
 def lbm_macroscopic(ctx, rho, u, dst_is_device):
@@ -333,6 +342,11 @@ class Lattice:
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
+
+    def step_timed(self, n):
+        """Advance n steps launch by launch; returns (sweep ms, exchange ms)
+        per launch, from HIP events on the context's stream."""
+        return lbm_step_timed(self.ctx, n)
 
     def macroscopic(self):
         rho = np.empty(self.shape)

@@ -105,6 +105,7 @@ def test_bad_tilings_rejected(blocks):
 def test_null_arguments_rejected():
     lib = _lib()
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_step_timed(None, 1, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_residual(None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert lib.lbm_bw_probe(None, None, 16, 1, None, None) == lbm.LBM_EINVAL

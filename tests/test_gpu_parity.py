@@ -185,6 +185,24 @@ def test_graph_steps_split_across_calls():
     assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
 
 
+@pytest.mark.parametrize("fused", [0, 1])
+def test_step_timed_matches_step(fused):
+    """The per-launch timed stepping advances the state exactly as lbm_step."""
+    dims = (16, 12, 10)
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 2), seed=3)
+    case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7)
+    blocks = inputs.uniform_blocks(dims, (2, 2, 1))
+    ref = run_gpu(case, 0, blocks=blocks, schedule=dict(fused_exchange=fused))
+    ref.step(9)
+    lat = run_gpu(case, 0, blocks=blocks, schedule=dict(fused_exchange=fused))
+    lat.step(2)
+    ts, te = lat.step_timed(5)
+    lat.step(2)
+    assert ts > 0 and (te > 0 if not fused else te == 0)
+    assert lat.info()["steps"] == 9
+    assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+
+
 # ------------------------------------------------------ sums, residual ----
 
 def test_sums_and_residual_match_oracle():

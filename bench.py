@@ -3,10 +3,11 @@
 Default workload: the force-driven plane Poiseuille channel, 256^3 cells,
 periodic in x and y, half-way bounce-back walls in z, g_x = 1e-6, tau = 0.8,
 started from rest, FP32 storage (and FP64 beside it).  One step = one sweep of
-every Block (pull, bounce-back, collision, fused ghost exchange) over the
-whole domain.  Prints one JSON line.
+every Block (pull, bounce-back, collision) over the whole domain plus the
+ghost-layer exchange (a separate kernel for one Block, fused into the sweep
+for several).  Median of 3 timed repeats.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--seed S]
 """
 import argparse
 import hashlib
@@ -44,23 +45,24 @@ def traffic_from_profile(name, src_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def workload(name):
+def workload(name, seed=0):
     from paper_1007_1388_amd import inputs
     p = inputs.preset(name)
     blocks = None
     solid = None
     if name == "porous512":
-        blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
-        solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
+        blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=seed)
+        solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=seed)
     return p, blocks, solid
 
 
 def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=None, autotune=None,
-             timed_launches=200):
+             timed_launches=200, repeats=3):
     """Timed region: `steps` steps (HIP-graph replays) bracketed by a
-    synchronize and HIP events on the context's stream.  Then
-    `timed_launches` further steps launched one by one with an event pair
-    around every kernel give the sweep kernel's own mean duration."""
+    synchronize and HIP events on the context's stream, `repeats` times in a
+    row; the median repeat counts.  Then `timed_launches` further steps
+    launched one by one with an event pair around every kernel give the
+    sweep kernel's own mean duration."""
     import torch
     from paper_1007_1388_amd import lbm
     lat = lbm.Lattice(p["dims"], blocks=blocks, walls=p["walls"], wall_u=p["wall_u"], tau=p["tau"],
@@ -76,20 +78,26 @@ def time_gpu(p, blocks, solid, precision, fp64_math, steps, warmup, schedule=Non
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    lat.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
+    walls, gpus = [], []
+    for _ in range(max(1, repeats)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        lat.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        gpus.append(e0.elapsed_time(e1))
+    order = sorted(range(len(walls)), key=lambda k: walls[k])
+    mid = order[len(order) // 2]
+    wall, gpu_ms = walls[mid], gpus[mid]
     sweep_ms, exch_ms = lat.step_timed(timed_launches) if timed_launches else (None, None)
     info = lat.info()
     sched = lat.schedule
     mass, _ = lat.sums()   # finite-check of the run (raises on instability)
     lat.close()
-    return dict(wall=wall, step_ms=gpu_ms / steps, sweep_ms=sweep_ms, exchange_ms=exch_ms, info=info,
-                schedule=sched, mass=mass)
+    return dict(wall=wall, walls=walls, step_ms=gpu_ms / steps, sweep_ms=sweep_ms, exchange_ms=exch_ms,
+                info=info, schedule=sched, mass=mass)
 
 
 def copy_probe(nbytes=1 << 30, reps=10):
@@ -132,9 +140,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--repeats", type=int, default=3, help="timed repeats of --steps steps; the median counts")
     ap.add_argument("--workload", default="poiseuille256",
                     choices=["poiseuille256", "porous512", "cavity384", "cavity32"])
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s", "bf16s"])
+    ap.add_argument("--seed", type=int, default=0, help="geometry and tiling seed of porous512")
     ap.add_argument("--fp64-math", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
@@ -157,12 +167,13 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_only, "copy_gbs": round(gbs, 1)}), flush=True)
         return
     copy_gbs = copy_probe()
-    p, blocks, solid = workload(args.workload)
+    p, blocks, solid = workload(args.workload, args.seed)
     prec = args.precision
     f64m = bool(args.fp64_math) and prec in ("f32", "f64")
     fused = args.fused if args.fused is not None else (0 if not blocks or len(blocks) == 1 else 1)
     sched = {"graph_steps": args.graph_steps, "fused_exchange": fused}
-    r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup, sched, args.autotune)
+    r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup, sched, args.autotune,
+                 repeats=args.repeats)
     info = r["info"]
     nf = info["n_fluid"]
     mlups = nf * args.steps / r["wall"] / 1e6
@@ -177,6 +188,10 @@ def main():
         arith = "f32 even part of feq/F; f64 velocity, odd part and update"
     else:
         arith = "f32 (storage %s, shifted)" % prec
+    if solid is not None:
+        extra = {"seed": args.seed, "solid_fraction": round(float(solid.mean()), 5)}
+    else:
+        extra = {}
     out = {
         "metric": "D3Q19 MLUPS (fluid lattice-cell updates per second, millions)",
         "value": round(mlups, 1),
@@ -185,6 +200,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["wall"] * 1e3 / args.steps, 5),
+        "repeats_ms_per_step": [round(w * 1e3 / args.steps, 5) for w in r["walls"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -193,7 +209,7 @@ def main():
         "config": {"workload": "%s %s" % (args.workload, "x".join(map(str, p["dims"]))),
                    "storage": prec, "arithmetic": arith,
                    "tau": p["tau"], "force": list(p["force"]), "blocks": info["n_blocks"],
-                   "fluid_cells": nf, "schedule": r["schedule"], "parallelism": "1 GPU"},
+                   "fluid_cells": nf, "schedule": r["schedule"], "parallelism": "1 GPU", **extra},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (round(tr / (r["sweep_ms"] * 1e-3) / 1e9, 1) if tr else None),
@@ -204,7 +220,7 @@ def main():
     }
     if not args.no_f64 and prec == "f32":
         n64 = max(1, args.steps // 2)
-        r64 = time_gpu(p, blocks, solid, "f64", False, n64, args.warmup, sched, args.autotune)
+        r64 = time_gpu(p, blocks, solid, "f64", False, n64, args.warmup, sched, args.autotune, repeats=1)
         i64 = r64["info"]
         m64 = i64["n_fluid"] * n64 / r64["wall"] / 1e6
         a64 = i64["n_fluid"] * i64["bytes_per_update"] / (r64["sweep_ms"] * 1e-3) / 1e9

@@ -81,6 +81,10 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);  /* optional device allocator */
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
+  int32_t row_pad;        /* x-row padding: every row of a Block array is rounded up to
+                             128 bytes and then row_pad more 128-byte lines are added;
+                             0 = automatic, -1 = none (layout only; results do not depend
+                             on it) */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -153,6 +157,22 @@ lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_de
  * measure).  Needs >= 2 steps since the last (re)initialisation, else
  * LBM_ESTATE.  Synchronises. */
 lbm_status lbm_residual(lbm_ctx* c, double* r);
+
+/* Velocity snapshot for residuals over several steps: stores u of the
+ * current state (FP64, 4 N doubles of device memory, allocated on first use
+ * through params.dev_alloc and kept until lbm_destroy).  Enqueued on
+ * params.stream; lbm_set_geometry, lbm_set_equilibrium and lbm_set_state
+ * discard the snapshot. */
+lbm_status lbm_residual_mark(lbm_ctx* c);
+
+/* r = ||u^n - u^m||_2 / ||u^n||_2 over fluid cells (FP64), u^m the snapshot of
+ * lbm_residual_mark taken n - m steps ago (written to *nsteps when non-NULL).
+ * With n - m even it is blind to the period-two population cycles that
+ * bounce-back sustains in cells whose open links lie in one plane (their
+ * momentum normal to that plane is reversed every step), which keep the
+ * one-step residual of lbm_residual from decaying in random porous media.
+ * LBM_ESTATE without a snapshot.  Synchronises. */
+lbm_status lbm_residual_since_mark(lbm_ctx* c, double* r, int64_t* nsteps);
 
 /* Global FP64 sums over fluid cells: mass = sum rho, mom = sum rho0 u. */
 lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]);

@@ -40,6 +40,12 @@ __host__ __device__ constexpr int OPPd(int i) {
   return t[i];
 }
 // lattice weight times a factor, from |e_i|^2
+// Representative index of the weight class of direction i (rest, face,
+// edge): the per-direction constant tables hold equal values within a
+// class, so reading one entry per class keeps the kernel's scalar
+// registers for what differs.
+__host__ __device__ constexpr int WCLS(int i) { return i == 0 ? 0 : (i < 7 ? 1 : 7); }
+
 __host__ __device__ constexpr double Wd(int i) {
   return (EXd(i) * EXd(i) + EYd(i) * EYd(i) + EZd(i) * EZd(i)) == 0   ? 1.0 / 3.0
          : (EXd(i) * EXd(i) + EYd(i) * EYd(i) + EZd(i) * EZd(i)) == 1 ? 1.0 / 18.0
@@ -471,16 +477,16 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
         if (EZd(i) < 0) eu -= uz[k];
       }
       // even part (shared by i and its opposite) and odd part (flips sign)
-      const C sym = ph.w[i] * fma(ph.rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
-      const C Fs = fma(ph.c9g[i], eu, -ph.w[i] * ug3[k]);
+      const C sym = ph.w[WCLS(i)] * fma(ph.rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
+      const C Fs = fma(ph.c9g[i], eu, -ph.w[WCLS(i)] * ug3[k]);
       const C even = fma(ph.omega, sym, ph.fcoef * Fs);
       if constexpr (HYB) {
-        const double odd = fma(ph.domega, ph.dc3w[i] * deu, ph.dcfa[i]);
+        const double odd = fma(ph.domega, ph.dc3w[WCLS(i)] * deu, ph.dcfa[i]);
         const double ev = (double)even;
         o0[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i][k]), ev + odd));
         o1[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i + 1][k]), ev - odd));
       } else {
-        const C odd = fma(ph.omega, ph.c3w[i] * eu, ph.cfa[i]);
+        const C odd = fma(ph.omega, ph.c3w[WCLS(i)] * eu, ph.cfa[i]);
         o0[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i][k]), even + odd));
         o1[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i + 1][k]), even - odd));
       }
@@ -743,8 +749,10 @@ __global__ void __launch_bounds__(256) k_macro(const void* grid_, CellArgs A, do
 }
 
 // Global FP64 sums: [0] sum drho, [1..3] sum rho0 u, [4] sum |u - u_prev|^2,
-// [5] sum |u|^2.  Per-workgroup partials; workgroup w always takes items w,
-// w + G, ... so the result is deterministic.
+// [5] sum |u|^2, with u_prev from the other grid (want_prev 1) or from a
+// stored FP64 velocity field um[3][N] (want_prev 2).  Per-workgroup
+// partials; workgroup w always takes items w, w + G, ... so the result is
+// deterministic.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -754,7 +762,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int PREC>
 __global__ void __launch_bounds__(256) k_reduce(const void* cur_, const void* prev_, CellArgs A, double rho0,
                                                 double hcx, double hcy, double hcz, double hpx, double hpy,
-                                                double hpz, int want_prev, double* __restrict__ partial) {
+                                                double hpz, int want_prev, const double* __restrict__ um,
+                                                long long N, double* __restrict__ partial) {
   using T = typename Stor<PREC>::T;
   const T* cur = (const T*)cur_;
   const T* prev = (const T*)prev_;
@@ -768,7 +777,7 @@ __global__ void __launch_bounds__(256) k_reduce(const void* cur_, const void* pr
       const double v = to_c<PREC, double>(cur[o]);
       d += v;
       jx += EXd(i) * v; jy += EYd(i) * v; jz += EZd(i) * v;
-      if (want_prev) {
+      if (want_prev == 1) {
         const double w = to_c<PREC, double>(prev[o]);
         px += EXd(i) * w; py += EYd(i) * w; pz += EZd(i) * w;
       }
@@ -776,8 +785,12 @@ __global__ void __launch_bounds__(256) k_reduce(const void* cur_, const void* pr
     const double ux = jx / rho0 - hcx, uy = jy / rho0 - hcy, uz = jz / rho0 - hcz;
     s[0] += d;
     s[1] += rho0 * ux; s[2] += rho0 * uy; s[3] += rho0 * uz;
-    if (want_prev) {
+    if (want_prev == 1) {
       const double dx = ux - (px / rho0 - hpx), dy = uy - (py / rho0 - hpy), dz = uz - (pz / rho0 - hpz);
+      s[4] += dx * dx + dy * dy + dz * dz;
+    } else if (want_prev == 2) {
+      const long long g = gidx(A.geo, B.org[0] + x, B.org[1] + y, B.org[2] + z);
+      const double dx = ux - um[g], dy = uy - um[N + g], dz = uz - um[2 * N + g];
       s[4] += dx * dx + dy * dy + dz * dz;
     }
     s[5] += ux * ux + uy * uy + uz * uz;
@@ -958,13 +971,14 @@ void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, co
 }
 
 void launch_reduce(int prec, const void* cur, const void* prev, const CellArgs& a, double rho0, const double hc[3],
-                   const double hp[3], int want_prev, double* partial, int nparts, double* out, hipStream_t s) {
+                   const double hp[3], int want_prev, const double* um, long long N, double* partial, int nparts,
+                   double* out, hipStream_t s) {
   dim3 g(nparts), b(256);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_reduce<0>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, partial); break;
-    case 1: hipLaunchKernelGGL(k_reduce<1>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, partial); break;
-    case 2: hipLaunchKernelGGL(k_reduce<2>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, partial); break;
-    default: hipLaunchKernelGGL(k_reduce<3>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, partial); break;
+    case 0: hipLaunchKernelGGL(k_reduce<0>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, um, N, partial); break;
+    case 1: hipLaunchKernelGGL(k_reduce<1>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, um, N, partial); break;
+    case 2: hipLaunchKernelGGL(k_reduce<2>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, um, N, partial); break;
+    default: hipLaunchKernelGGL(k_reduce<3>, g, b, 0, s, cur, prev, a, rho0, hc[0], hc[1], hc[2], hp[0], hp[1], hp[2], want_prev, um, N, partial); break;
   }
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, nparts, out);
 }

@@ -36,7 +36,8 @@ void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const 
 void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, const double hg[3], double* rho,
                   double* u, long long N, hipStream_t s);
 void launch_reduce(int prec, const void* cur, const void* prev, const CellArgs& a, double rho0, const double hc[3],
-                   const double hp[3], int want_prev, double* partial, int nparts, double* out, hipStream_t s);
+                   const double hp[3], int want_prev, const double* um, long long N, double* partial, int nparts,
+                   double* out, hipStream_t s);
 void launch_get_state(int prec, bool f64, const void* grid, const CellArgs& a, void* out, long long N,
                       hipStream_t s);
 void launch_set_state(int prec, bool f64, void* grid, const CellArgs& a, const void* in, long long N,
@@ -115,6 +116,8 @@ struct lbm_ctx {
   int nparts = 1024;
   double* d_red = nullptr;
   void* d_stage = nullptr;
+  double* d_umark = nullptr;   // [rho | u_x | u_y | u_z] snapshot, FP64, 4 N
+  long long mark_steps = -1;   // step count of the snapshot, -1 = none
   size_t stage_bytes = 0;
 
   int cur = 0;
@@ -434,14 +437,25 @@ void half_force(const lbm_ctx* c, bool post, double hg[3]) {
   for (int k = 0; k < 3; ++k) hg[k] = post ? 0.5 * c->p.force[k] : 0.0;
 }
 
-lbm_status reduce(lbm_ctx* c, bool want_prev, double out[6]) {
+// want_prev: 0 sums only, 1 against the other grid (previous step), 2 against
+// the velocity snapshot of lbm_residual_mark.
+// Extra 128-byte lines appended to every x-row (lbm_params.row_pad).
+long long row_pad_lines(const lbm_params& p, long long row_bytes) {
+  if (p.row_pad < 0) return 0;
+  if (p.row_pad > 0) return p.row_pad;
+  (void)row_bytes;
+  return 0;
+}
+
+lbm_status reduce(lbm_ctx* c, int want_prev, double out[6]) {
   double hc[3], hp[3];
   half_force(c, c->steps >= 1, hc);
   half_force(c, c->steps >= 2, hp);
   const CellArgs a = cell_args(c);
   const int nparts = std::max(1, std::min(c->nparts, a.nitems));
-  launch_reduce(c->prec, c->grid[c->cur], c->grid[1 - c->cur], a, c->p.rho0, hc, hp, want_prev ? 1 : 0,
-                c->d_partial, nparts, c->d_red, c->stream);
+  launch_reduce(c->prec, c->grid[c->cur], c->grid[1 - c->cur], a, c->p.rho0, hc, hp, want_prev,
+                want_prev == 2 ? c->d_umark + c->n_cells : nullptr, c->n_cells, c->d_partial, nparts, c->d_red,
+                c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(out, c->d_red, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -517,6 +531,7 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
   if (p->precision < LBM_F64 || p->precision > LBM_BF16S) return fail(LBM_EINVAL, "bad precision");
+  if (p->row_pad < -1 || p->row_pad > 64) return fail(LBM_EINVAL, "row_pad must be in [-1, 64]");
   for (int k = 0; k < 3; ++k) {
     if (!std::isfinite(p->force[k])) return fail(LBM_EINVAL, "force must be finite");
     const int f0 = p->face[2 * k], f1 = p->face[2 * k + 1];
@@ -646,7 +661,7 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       B.org[k] = blocks[j].lo[k];
       B.dim[k] = blocks[j].hi[k] - blocks[j].lo[k];
     }
-    B.Sx = (int)roundup(B.dim[0], align);
+    B.Sx = (int)(roundup(B.dim[0], align) + row_pad_lines(*p, B.dim[0] * (long long)c->sbytes) * align);
     B.Ry = B.dim[1] + 2;
     B.Sz = (long long)B.Sx * (B.dim[1] + 2);
     // array (with y/z ghost layer), one spare row, then its x-ghost plane
@@ -780,6 +795,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cur = 0;
   c->steps = 0;
+  c->mark_steps = -1;
   return LBM_OK;
 }
 
@@ -796,6 +812,7 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 0;
+  c->mark_steps = -1;
   return LBM_OK;
 }
 
@@ -873,17 +890,44 @@ lbm_status lbm_residual(lbm_ctx* c, double* r) {
   if (!c || !r) return fail(LBM_EINVAL, "NULL argument");
   if (c->steps < 2) return fail(LBM_ESTATE, "residual needs >= 2 steps since initialisation");
   double s[6];
-  lbm_status st = reduce(c, true, s);
+  lbm_status st = reduce(c, 1, s);
   if (st != LBM_OK) return st;
   *r = std::sqrt(s[4]) / std::sqrt(s[5]);
   if (!std::isfinite(*r)) *r = s[4] == 0.0 ? 0.0 : INFINITY;
   return LBM_OK;
 }
 
+lbm_status lbm_residual_mark(lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (!c->d_umark) {
+    c->d_umark = (double*)dalloc(c, 4 * (size_t)c->n_cells * sizeof(double));
+    if (!c->d_umark) return fail(LBM_ENOMEM, "velocity snapshot allocation failed");
+  }
+  double hg[3];
+  half_force(c, c->steps >= 1, hg);
+  launch_macro(c->prec, c->grid[c->cur], cell_args(c), c->p.rho0, hg, c->d_umark, c->d_umark + c->n_cells,
+               c->n_cells, c->stream);
+  HIPCHK(hipGetLastError());
+  c->mark_steps = c->steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_residual_since_mark(lbm_ctx* c, double* r, int64_t* nsteps) {
+  if (!c || !r) return fail(LBM_EINVAL, "NULL argument");
+  if (c->mark_steps < 0) return fail(LBM_ESTATE, "no velocity snapshot since the last (re)initialisation");
+  double s[6];
+  lbm_status st = reduce(c, 2, s);
+  if (st != LBM_OK) return st;
+  *r = std::sqrt(s[4]) / std::sqrt(s[5]);
+  if (!std::isfinite(*r)) *r = s[4] == 0.0 ? 0.0 : INFINITY;
+  if (nsteps) *nsteps = c->steps - c->mark_steps;
+  return LBM_OK;
+}
+
 lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]) {
   if (!c || !mass || !mom) return fail(LBM_EINVAL, "NULL argument");
   double s[6];
-  lbm_status st = reduce(c, false, s);
+  lbm_status st = reduce(c, 0, s);
   if (st != LBM_OK) return st;
   *mass = (double)c->n_fluid * c->p.rho0 + s[0];
   mom[0] = s[1];
@@ -917,6 +961,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 1;
+  c->mark_steps = -1;
   return LBM_OK;
 }
 

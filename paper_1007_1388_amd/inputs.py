@@ -68,6 +68,104 @@ def porous_spheres(dims, target_fraction=0.10, radius=(3, 8), seed=0,
     return solid.astype(np.uint8)
 
 
+def fill_isolated_pores(solid, periodic=(True, True, False)):
+    """Make solid every fluid cell outside the largest connected pore space.
+
+    solid: uint8 [nz, ny, nx].  Two fluid cells are connected when one of
+    the 18 D3Q19 links joins them (across the faces flagged ``periodic``,
+    taken as (x, y, z)).  A pocket that no link joins to the main pore space
+    carries no flow, and with a body force it keeps a population cycle of
+    period two (bounce-back reverses its momentum every step), so it is
+    filled.  Returns a new uint8 array.
+    """
+    from scipy import ndimage
+    sol = np.asarray(solid, dtype=bool)
+    fluid = ~sol
+    struct = np.ones((3, 3, 3), dtype=bool)
+    for c in [(0, 0, 0), (0, 0, 2), (0, 2, 0), (0, 2, 2), (2, 0, 0), (2, 0, 2), (2, 2, 0), (2, 2, 2)]:
+        struct[c] = False
+    pz, py, px = (1 if periodic[2] else 0), (1 if periodic[1] else 0), (1 if periodic[0] else 0)
+    padded = np.pad(fluid, ((pz, pz), (py, py), (px, px)), mode="wrap")
+    lab, n = ndimage.label(padded, structure=struct)
+    if n == 0:
+        return sol.astype(np.uint8)
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    # a padded cell is the periodic image of an interior cell: join their labels
+    nz, ny, nx = fluid.shape
+    zz, yy, xx = np.nonzero(lab)
+    inner = lab[pz:pz + nz, py:py + ny, px:px + nx]
+    img = inner[(zz - pz) % nz, (yy - py) % ny, (xx - px) % nx]
+    for a, b in set(zip(lab[zz, yy, xx].tolist(), img.tolist())):
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[ra] = rb
+    roots = np.array([find(k) for k in range(n + 1)])
+    comp = roots[inner]
+    comp[~fluid] = 0
+    counts = np.bincount(comp.ravel())
+    counts[0] = 0
+    keep = int(np.argmax(counts))
+    out = sol | (comp != keep)
+    return out.astype(np.uint8)
+
+
+_LINKS = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+          (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+          (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+def fill_trapped_cells(solid, periodic=(True, True, False)):
+    """Fill fluid cells whose open links do not span 3-D space, repeatedly,
+    then the pores outside the main pore space (``fill_isolated_pores``).
+
+    solid: uint8 [nz, ny, nx]; non-periodic faces count as walls.  In a cell
+    whose open link directions e (neighbour x + e fluid) all lie in one plane,
+    the momentum component normal to that plane is conserved by the
+    collision and reversed by bounce-back on every step, so it oscillates
+    with period two and never decays; a body force feeds it.  The test is
+    det(sum over open links of e e^T) == 0, exact in integers.  Returns a new
+    uint8 array.
+    """
+    sol = np.asarray(solid, dtype=bool).copy()
+    nz, ny, nx = sol.shape
+    while True:
+        fluid = ~sol
+        G = np.zeros((6,) + sol.shape, dtype=np.int64)  # xx, yy, zz, xy, xz, yz
+        for ex, ey, ez in _LINKS:
+            nb = fluid
+            for axis, e in ((2, ex), (1, ey), (0, ez)):
+                if e == 0:
+                    continue
+                per = periodic[2 - axis]
+                nb = np.roll(nb, -e, axis=axis)   # nb[c] = fluid[c + e]
+                if not per:
+                    idx = [slice(None)] * 3
+                    idx[axis] = slice(-1, None) if e > 0 else slice(0, 1)
+                    nb = nb.copy()
+                    nb[tuple(idx)] = False
+            o = nb.astype(np.int64)
+            G[0] += o * ex * ex
+            G[1] += o * ey * ey
+            G[2] += o * ez * ez
+            G[3] += o * ex * ey
+            G[4] += o * ex * ez
+            G[5] += o * ey * ez
+        xx, yy, zz, xy, xz, yz = G
+        det = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz)
+        bad = fluid & (det == 0)
+        if not bad.any():
+            break
+        sol |= bad
+    return fill_isolated_pores(sol.astype(np.uint8), periodic)
+
+
 def channel_obstacle(dims, center=None, radius=3):
     """One sphere obstacle in a channel (deterministic), uint8 [nz, ny, nx]."""
     nx, ny, nz = dims

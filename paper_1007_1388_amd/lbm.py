@@ -47,7 +47,7 @@ class lbm_params(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
                 ("precision", ctypes.c_int32), ("fp64_math", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", ctypes.c_void_p)]
+                ("alloc_user", ctypes.c_void_p), ("row_pad", ctypes.c_int32)]
 
 
 class lbm_schedule(ctypes.Structure):
@@ -72,7 +72,8 @@ class lbm_info(ctypes.Structure):
 
 # The exported symbols of include/lbm.h, in declaration order.
 SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step",
-           "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_sums", "lbm_get_state", "lbm_set_state",
+           "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
+           "lbm_sums", "lbm_get_state", "lbm_set_state",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_autotune", "lbm_info_get", "lbm_destroy",
            "lbm_strerror", "lbm_last_error", "lbm_bw_probe"]
 
@@ -103,6 +104,8 @@ def load(path=LIB_PATH):
         "lbm_step_timed": [P, ctypes.c_int64, dp, dp],
         "lbm_macroscopic": [P, P, P, ctypes.c_int32],
         "lbm_residual": [P, dp],
+        "lbm_residual_mark": [P],
+        "lbm_residual_since_mark": [P, dp, ctypes.POINTER(ctypes.c_int64)],
         "lbm_sums": [P, dp, dp],
         "lbm_get_state": [P, P, ctypes.c_int32],
         "lbm_set_state": [P, P, ctypes.c_int32],
@@ -185,6 +188,17 @@ def lbm_residual(ctx):
     return r.value
 
 
+def lbm_residual_mark(ctx):
+    _check(load().lbm_residual_mark(ctx), "lbm_residual_mark")
+
+
+def lbm_residual_since_mark(ctx):
+    r = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().lbm_residual_since_mark(ctx, ctypes.byref(r), ctypes.byref(n)), "lbm_residual_since_mark")
+    return r.value, n.value
+
+
 def lbm_sums(ctx):
     m = ctypes.c_double()
     p = (ctypes.c_double * 3)()
@@ -241,7 +255,7 @@ def lbm_bw_probe(dst_ptr, src_ptr, nbytes, reps, stream):
 # ----------------------------------------------------------- convenience ---
 
 def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.0,
-                force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False, stream=None):
+                force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False, stream=None, row_pad=0):
     p = lbm_params()
     p.dims[:] = [int(d) for d in dims]
     for k in range(3):
@@ -257,6 +271,7 @@ def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.fp64_math = 1 if fp64_math else 0
     p.stream = stream
+    p.row_pad = int(row_pad)
     return p
 
 
@@ -292,7 +307,7 @@ class Lattice:
 
     def __init__(self, dims, blocks=None, walls=(False, False, False), wall_u=None, tau=0.6,
                  rho0=1.0, force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False,
-                 stream=None, torch_alloc=True):
+                 stream=None, torch_alloc=True, row_pad=0):
         load()
         import torch
         if not torch.cuda.is_available():
@@ -307,7 +322,8 @@ class Lattice:
         if blocks is None:
             blocks = [((0, 0, 0), self.dims)]
         self.blocks = [tuple(map(tuple, b)) for b in blocks]
-        self.params = make_params(dims, walls, wall_u, tau, rho0, force, precision, fp64_math, stream)
+        self.params = make_params(dims, walls, wall_u, tau, rho0, force, precision, fp64_math, stream,
+                                  row_pad)
         self._alloc = None
         if torch_alloc:
             self._alloc = _TorchAllocator(stream)
@@ -363,6 +379,14 @@ class Lattice:
 
     def residual(self):
         return lbm_residual(self.ctx)
+
+    def residual_mark(self):
+        """Snapshot the current velocity field for residual_since_mark."""
+        lbm_residual_mark(self.ctx)
+
+    def residual_since_mark(self):
+        """(||u^n - u^mark|| / ||u^n||, steps since the mark)."""
+        return lbm_residual_since_mark(self.ctx)
 
     def sums(self):
         return lbm_sums(self.ctx)

@@ -1,0 +1,101 @@
+"""Size and Block-count sweeps of the D3Q19 sweep on one GPU.
+
+  python -m paper_1007_1388_amd.sweeps size   [--steps 200]   # single-Block periodic cubes
+  python -m paper_1007_1388_amd.sweeps blocks [--steps 200]   # 384^3 split into 1..216 Blocks, porous
+
+size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
+        storage, started from rest with g_x = 1e-6, tau 0.8: MLUPS against N,
+        the single-Block scaling study of Sec. 5.1.
+blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
+        the 512x256x256 porous channel as its uneven Blocks; per-launch times
+        of the sweep and of the separate ghost exchange (HIP events), and the
+        step time with the exchange fused into the sweep: the cost of Blocks
+        and of their on-GPU copies, Sec. 5.2.
+
+Prints one JSON line per case.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_1007_1388_amd import inputs, lbm  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def measure(dims, precision, steps, blocks=None, solid=None, walls=(False, False, False), tau=0.8,
+            force=(1e-6, 0.0, 0.0), fused=0, graph_steps=10):
+    import torch
+    lat = lbm.Lattice(dims, blocks=blocks, walls=walls, tau=tau, force=force, precision=precision)
+    if solid is not None:
+        lat.set_geometry(solid)
+    lat.set_schedule(fused_exchange=fused, graph_steps=graph_steps)
+    lat.step(20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    sweep_ms, exch_ms = lat.step_timed(min(steps, 100))
+    info = lat.info()
+    lat.sums()
+    lat.close()
+    nf = info["n_fluid"]
+    return dict(step_ms=round(step_ms, 5), sweep_ms=round(sweep_ms, 5), exchange_ms=round(exch_ms, 5),
+                mlups=round(nf / step_ms / 1e3, 1),
+                sweep_gbs=round(nf * info["bytes_per_update"] / (sweep_ms * 1e-3) / 1e9, 1),
+                frac=round(nf * info["bytes_per_update"] / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                blocks=info["n_blocks"], fluid_cells=nf)
+
+
+def size_sweep(steps, sizes):
+    for n in sizes:
+        for prec in ("f32", "f64"):
+            r = measure((n, n, n), prec, steps)
+            print(json.dumps(dict(study="size", n=n, precision=prec, **r)), flush=True)
+
+
+def block_sweep(steps):
+    n = 384
+    for k in (1, 2, 3, 4, 6):
+        blocks = inputs.uniform_blocks((n, n, n), (k, k, k))
+        for fused in (0, 1):
+            r = measure((n, n, n), "f32", steps, blocks=blocks, fused=fused)
+            print(json.dumps(dict(study="blocks", domain="384^3 periodic", split="%dx%dx%d" % (k, k, k),
+                                  precision="f32", fused=fused, **r)), flush=True)
+    p = inputs.preset("porous512")
+    blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
+    solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
+    for fused in (0, 1):
+        r = measure(p["dims"], "f32", steps, blocks=blocks, solid=solid, walls=p["walls"], tau=p["tau"],
+                    force=p["force"], fused=fused)
+        print(json.dumps(dict(study="blocks", domain="porous 512x256x256", split="uneven {32,48,64}",
+                              precision="f32", fused=fused, **r)), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["size", "blocks"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--sizes", default="64-512:32")
+    args = ap.parse_args()
+    import torch
+    torch.cuda.init()
+    if args.study == "size":
+        lo, rest = args.sizes.split("-")
+        hi, st = rest.split(":")
+        size_sweep(args.steps, range(int(lo), int(hi) + 1, int(st)))
+    else:
+        block_sweep(args.steps)
+
+
+if __name__ == "__main__":
+    main()

@@ -3,9 +3,10 @@
   python -m paper_1007_1388_amd.warmstart [--train N] [--test M] [--epochs E] [--out report.json]
 
 1. Data: N porous channels 64 x 64 x 128 (x, y periodic, walls in z), solid
-   fraction uniform in [5 %, 20 %], sphere radii 3..8, g_x log-uniform in
+   fraction uniform in [5 %, 20 %], sphere radii 3..8 (trapped cells and
+   isolated pores filled, see inputs.fill_trapped_cells), g_x log-uniform in
    [5e-7, 5e-6], tau 0.7, each run from rest by the lattice Boltzmann solver
-   until the residual ||u^n - u^(n-1)|| / ||u^n|| drops below 1e-6.
+   until the residual ||u^n - u^(n-2)|| / (2 ||u^n||) drops below 1e-6.
 2. Training: the U-Net of surrogate.py on (mask, g_x) -> (u, rho - rho0)/g_x,
    BF16 MFMA kernels, FP32 master weights, Adam, masked MSE on fluid cells.
 3. Evaluation on M held-out seeds: steps and wall time to residual 1e-6 from
@@ -41,7 +42,10 @@ def sample(seed):
     frac = float(rng.uniform(0.05, 0.20))
     gx = float(10 ** rng.uniform(np.log10(5e-7), np.log10(5e-6)))
     solid = inputs.porous_spheres(DIMS, target_fraction=frac, radius=(3, 8), seed=seed)
-    return solid, gx, frac
+    # cells with undamped period-two momentum (and pockets) would keep the
+    # step-to-step residual from ever reaching the tolerance
+    solid = inputs.fill_trapped_cells(solid)
+    return solid, gx, float(solid.mean())
 
 
 def make_lattice(gx, solid, stream):
@@ -52,9 +56,12 @@ def make_lattice(gx, solid, stream):
     return lat
 
 
-def run_to_steady(lats, check_every=20, max_steps=400_000):
-    """Step several lattices (each on its own stream) until each one's residual
-    is below TOL; returns per-lattice (steps, seconds)."""
+def run_to_steady(lats, check_every=100, max_steps=400_000):
+    """Step several lattices (each on its own stream) until each one's
+    steady-state residual ||u^n - u^(n-2)|| / (2 ||u^n||) is below TOL;
+    returns per-lattice (steps, seconds, residual).  The two-step difference
+    per step is the rate of change with the period-two cycles of trapped
+    bounce-back cells filtered out."""
     import torch
     n = len(lats)
     done = [None] * n
@@ -63,11 +70,14 @@ def run_to_steady(lats, check_every=20, max_steps=400_000):
     while any(d is None for d in done):
         for k, lat in enumerate(lats):
             if done[k] is None:
-                lat.step(check_every)
+                lat.step(check_every - 2)
+                lat.residual_mark()
+                lat.step(2)
                 steps[k] += check_every
         for k, lat in enumerate(lats):
             if done[k] is None:
-                r = lat.residual()
+                r2, m = lat.residual_since_mark()
+                r = r2 / m
                 if r < TOL or steps[k] >= max_steps or not math.isfinite(r):
                     done[k] = (steps[k], time.perf_counter() - t0[k], r)
     torch.cuda.synchronize()
@@ -261,6 +271,7 @@ def main():
     t0 = time.perf_counter()
     data = generate(list(range(args.train)), concurrent=args.concurrent, log=log)
     t_gen = time.perf_counter() - t0
+    log("generation %.1f s" % t_gen)
     for d in data:
         d["fluid"] = int((d["solid"] == 0).sum().item())
     tr = Trainer(batch=args.batch)

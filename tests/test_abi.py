@@ -68,7 +68,7 @@ BOX = [((0, 0, 0), (8, 8, 8))]
 
 @pytest.mark.parametrize("bad", [
     dict(tau=0.5), dict(tau=0.4), dict(tau=float("nan")), dict(rho0=0.0), dict(dims=(0, 8, 8)),
-    dict(precision=7), dict(force=(float("inf"), 0, 0)),
+    dict(precision=7), dict(force=(float("inf"), 0, 0)), dict(row_pad=-2), dict(row_pad=65),
 ])
 def test_invalid_parameters_are_rejected(bad):
     kw = dict(dims=(8, 8, 8), tau=0.7)
@@ -107,5 +107,7 @@ def test_null_arguments_rejected():
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_step_timed(None, 1, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_residual(None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_residual_mark(None) == lbm.LBM_EINVAL
+    assert lib.lbm_residual_since_mark(None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert lib.lbm_bw_probe(None, None, 16, 1, None, None) == lbm.LBM_EINVAL

@@ -203,7 +203,59 @@ def test_step_timed_matches_step(fused):
     assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_row_padding_is_layout_only(precision):
+    """Extra x-row padding changes addresses only: bitwise equal states."""
+    dims = (24, 12, 10)
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 2), seed=6)
+    case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7)
+    blocks = inputs.uniform_blocks(dims, (2, 2, 1))
+    states = []
+    for pad in (-1, 1, 3):
+        lat = gpu_lattice(case, blocks=blocks, precision=precision, row_pad=pad)
+        prepare(lat, case)
+        lat.step(12)
+        states.append(lat.get_state(as_fp64=False))
+        lat.close()
+    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
+
+
 # ------------------------------------------------------ sums, residual ----
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_residual_since_mark(precision):
+    """One step after the mark it is the one-step residual, bit for bit; two
+    steps after, it matches the oracle's ||u^n - u^(n-2)|| / ||u^n||."""
+    dims = (16, 12, 10)
+    solid = inputs.porous_spheres(dims, target_fraction=0.15, radius=(1, 2), seed=4)
+    case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7)
+    lat = run_gpu(case, 0, blocks=inputs.uniform_blocks(dims, (2, 1, 2)), precision=precision)
+    from paper_1007_1388_amd.lbm import LBMError
+    with pytest.raises(LBMError):
+        lat.residual_since_mark()
+    lat.step(6)
+    lat.residual_mark()
+    lat.step(1)
+    r1, n1 = lat.residual_since_mark()
+    assert n1 == 1 and r1 == lat.residual()
+    o = run_oracle(case, 0)
+    o.step(5)
+    _, u_a = o.macroscopic()
+    o.step(2)
+    _, u_b = o.macroscopic()
+    fl = solid == 0
+    r_ref = np.linalg.norm((u_b - u_a)[:, fl]) / np.linalg.norm(u_b[:, fl])
+    lat2 = run_gpu(case, 0, blocks=inputs.uniform_blocks(dims, (2, 1, 2)), precision=precision)
+    lat2.step(5)
+    lat2.residual_mark()
+    lat2.step(2)
+    r2, n2 = lat2.residual_since_mark()
+    assert n2 == 2
+    assert abs(r2 - r_ref) <= (1e-10 if precision == "f64" else 1e-4) * r_ref, (r2, r_ref)
+    lat2.set_geometry(solid)  # re-initialisation discards the snapshot
+    with pytest.raises(LBMError):
+        lat2.residual_since_mark()
+
 
 def test_sums_and_residual_match_oracle():
     dims = (16, 12, 10)

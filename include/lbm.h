@@ -100,6 +100,10 @@ typedef struct {
                               compute unit loop over the item list */
   int32_t graph_steps;     /* time steps per captured HIP graph; 0: plain launches */
   int32_t nontemporal;     /* 1: streaming (non-temporal) loads and stores */
+  int32_t cells_per_lane;  /* cells per lane along x: 0 = automatic (1); 1; or 2 (only for
+                              F16S/BF16S and for F32 storage with FP64 arithmetic, with
+                              every Block's x extent even, else LBM_EINVAL).  Results do
+                              not depend on it. */
 } lbm_schedule;
 
 typedef struct {

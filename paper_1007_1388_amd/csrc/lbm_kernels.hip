@@ -60,13 +60,9 @@ template <> struct Stor<2> { using T = uint16_t; };  // IEEE binary16 bits
 template <> struct Stor<3> { using T = uint16_t; };  // bfloat16 bits
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// round-to-nearest-even float -> bfloat16 (NaN kept quiet)
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even: gfx950's conversion instruction
+// (two conversions of a lane pack into one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 // float -> binary16, round to nearest even.  Written as the conversion
 // instruction itself so the compiler cannot merge it with the preceding FMA
@@ -891,18 +887,14 @@ static SweepFn pick3(bool mask, bool fused, bool nt) {
   return nt ? launch_sweep_t<PREC, C, false, false, true, VEC> : launch_sweep_t<PREC, C, false, false, false, VEC>;
 }
 
-// Cells per lane along x when every Block's x extent allows it (vec_ok),
-// else one: two for 16-bit storage (four bytes per lane and stream, like
-// FP32) and for FP32 storage with FP64 arithmetic.
-int sweep_vec(int prec, bool f64math, bool vec_ok) {
-  if (!vec_ok) return 1;
-  return (prec >= 2 || (prec == 1 && f64math)) ? 2 : 1;
-}
+// Storage modes with a two-cells-per-lane sweep: 16-bit storage (four bytes
+// per lane and stream, like FP32) and FP32 storage with FP64 arithmetic.
+bool sweep_vec2_ok(int prec, bool f64math) { return prec >= 2 || (prec == 1 && f64math); }
 
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
-  const bool v = sweep_vec(prec, f64math, vec_ok) > 1;
+  const bool v = vec == 2 && sweep_vec2_ok(prec, f64math);
   switch (prec) {
     case 0: fn = pick3<0, double, 1>(mask, fused, nt); break;
     case 1:

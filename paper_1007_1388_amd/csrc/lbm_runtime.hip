@@ -23,9 +23,9 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, bool vec_ok, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
-int sweep_vec(int prec, bool f64math, bool vec_ok);
+bool sweep_vec2_ok(int prec, bool f64math);
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
                      int ntasks, int max_cells, const uint32_t* mask, hipStream_t s);
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
@@ -111,7 +111,7 @@ struct lbm_ctx {
   XchgTask* d_tasks = nullptr;
   uint32_t* d_mask = nullptr;
   bool has_mask = false;
-  bool vec_ok = false;   // every Block's x extent is a multiple of the vector width
+  bool x_even = false;   // every Block's x extent is even (two cells per lane possible)
   double* d_partial = nullptr;
   int nparts = 1024;
   double* d_red = nullptr;
@@ -348,6 +348,14 @@ void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
   launch_bbfill(c->prec, c->f64math, c->grid[g], cell_args(c), c->phd, c->phf, s);
 }
 
+// Cells per lane the sweep of schedule s runs with (0 = automatic = one: with
+// a single cell per lane the sweep keeps more waves resident and measured
+// faster for every storage mode on gfx950).
+int cells_per_lane(const lbm_ctx* c, const lbm_schedule& s) {
+  const bool two_ok = c->x_even && sweep_vec2_ok(c->prec, c->f64math);
+  return s.cells_per_lane == 2 && two_ok ? 2 : 1;
+}
+
 void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   const SweepArgs a = sweep_args(c, from);
   const int nitems = (int)c->items_h.size();
@@ -355,7 +363,7 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
   launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0,
-               c->vec_ok, a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+               cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
@@ -473,7 +481,7 @@ lbm_status zero_grids(lbm_ctx* c) {
 std::string sched_str(const lbm_schedule& s) {
   std::ostringstream o;
   o << s.fused_exchange << " " << s.item_cells << " " << s.wg_size << " " << s.persistent << " " << s.graph_steps
-    << " " << s.nontemporal;
+    << " " << s.nontemporal << " " << s.cells_per_lane;
   return o.str();
 }
 
@@ -489,6 +497,10 @@ bool sched_valid(const lbm_schedule& s, std::string& err) {
   }
   if (s.persistent < 0 || s.persistent > 64 || s.graph_steps < 0 || s.graph_steps > 4096) {
     err = "persistent or graph_steps out of range";
+    return false;
+  }
+  if (s.cells_per_lane < 0 || s.cells_per_lane > 2) {
+    err = "cells_per_lane must be 0, 1 or 2";
     return false;
   }
   return true;
@@ -674,12 +686,9 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     B.mask = -1;
   }
   c->grid_elems = (size_t)off;
-  {
-    const int vw = sweep_vec(c->prec, c->f64math, true);
-    c->vec_ok = true;
-    for (const auto& B : c->bh)
-      if (B.dim[0] % vw) c->vec_ok = false;
-  }
+  c->x_even = true;
+  for (const auto& B : c->bh)
+    if (B.dim[0] % 2) c->x_even = false;
 
   // neighbour table: Block across each face/edge/corner, with translation
   c->nbh.assign((size_t)nblocks * 27, NbrDev{-1, 0, 0, 0});
@@ -716,6 +725,7 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->sched.persistent = 0;
   c->sched.graph_steps = 0;
   c->sched.nontemporal = 1;
+  c->sched.cells_per_lane = 0;
   build_items(c);
   build_tasks(c);
 
@@ -975,6 +985,8 @@ lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s) {
   if (!c || !s) return fail(LBM_EINVAL, "NULL argument");
   std::string err;
   if (!sched_valid(*s, err)) return fail(LBM_EINVAL, err);
+  if (s->cells_per_lane == 2 && !(c->x_even && sweep_vec2_ok(c->prec, c->f64math)))
+    return fail(LBM_EINVAL, "two cells per lane need F16S/BF16S (or F32 with FP64 math) and even x extents");
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   const lbm_schedule old = c->sched;
@@ -1033,7 +1045,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
       std::string kk;
       lbm_schedule s{};
       if (ls >> kk >> s.fused_exchange >> s.item_cells >> s.wg_size >> s.persistent >> s.graph_steps >>
-          s.nontemporal) {
+          s.nontemporal >> s.cells_per_lane) {
         std::string err;
         if (kk == k && sched_valid(s, err)) {
           lbm_status st = lbm_set_schedule(c, &s);
@@ -1078,7 +1090,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
   const std::vector<int> wgs = {64, 128, 256};
   const std::vector<int> pers = {0, 2, 4, 8, 16};
   for (int pass = 0; pass < 2 && st == LBM_OK; ++pass) {
-    for (int knob = 0; knob < 5 && st == LBM_OK; ++knob) {
+    for (int knob = 0; knob < 6 && st == LBM_OK; ++knob) {
       std::vector<lbm_schedule> cand;
       for (size_t q = 0; q < (knob == 0 ? cells.size() : knob == 1 ? wgs.size() : knob == 2 ? pers.size() : 2);
            ++q) {
@@ -1088,6 +1100,10 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
         if (knob == 2) s.persistent = pers[q];
         if (knob == 3) s.nontemporal = (int)q;
         if (knob == 4) s.fused_exchange = (int)q;
+        if (knob == 5) {
+          if (!(c->x_even && sweep_vec2_ok(c->prec, c->f64math))) continue;
+          s.cells_per_lane = (int)q + 1;
+        }
         cand.push_back(s);
       }
       for (const auto& s : cand) {

@@ -53,7 +53,8 @@ class lbm_params(ctypes.Structure):
 class lbm_schedule(ctypes.Structure):
     _fields_ = [("fused_exchange", ctypes.c_int32), ("item_cells", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("cells_per_lane", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -147,11 +147,12 @@ TILINGS = {
 @pytest.mark.parametrize("tiling", sorted(TILINGS))
 @pytest.mark.parametrize("dims", [(13, 12, 10), (24, 12, 10)])
 def test_partition_invariance_bitwise(precision, tiling, dims):
-    # x = 24 lets the single Block use several cells per lane; most tilings
-    # then fall back to one cell per lane: both must round alike.
+    # With x = 24 the single-Block reference of the 16-bit formats runs two
+    # cells per lane; the tilings run one: both must round alike.
     solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 3), seed=2)
     case = channel(dims=dims, solid=solid, force=(1e-5, 0, 3e-6), tau=0.75, seed=4)
-    ref = run_gpu(case, 25, precision=precision)
+    two = precision in ("f16s", "bf16s") and dims[0] % 2 == 0
+    ref = run_gpu(case, 25, precision=precision, schedule=dict(cells_per_lane=2) if two else None)
     lat = run_gpu(case, 25, blocks=TILINGS[tiling](dims), precision=precision)
     assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
 
@@ -183,6 +184,36 @@ def test_graph_steps_split_across_calls():
     for n in (1, 2, 0, 4):
         lat.step(n)
     assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+
+
+@pytest.mark.parametrize("precision,f64m", [("f16s", False), ("bf16s", False), ("f32", True)])
+def test_cells_per_lane_bitwise(precision, f64m):
+    """One or two cells per lane: identical rounding, identical states."""
+    dims = (24, 12, 10)
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 2), seed=9)
+    case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7)
+    blocks = inputs.uniform_blocks(dims, (2, 2, 1))
+    out = []
+    for cpl in (1, 2, 0):
+        lat = run_gpu(case, 0, blocks=blocks, precision=precision, fp64_math=f64m,
+                      schedule=dict(cells_per_lane=cpl, fused_exchange=cpl % 2))
+        lat.step(15)
+        out.append(lat.get_state(as_fp64=False))
+        lat.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_cells_per_lane_two_rejected_where_unsupported():
+    from paper_1007_1388_amd.lbm import LBMError
+    lat = gpu_lattice(channel(dims=(23, 8, 6)), precision="f16s")  # odd x extent
+    with pytest.raises(LBMError):
+        lat.set_schedule(cells_per_lane=2)
+    lat.close()
+    lat = gpu_lattice(channel(dims=(24, 8, 6)), precision="f32")  # mixed FP32 math: one cell per lane
+    with pytest.raises(LBMError):
+        lat.set_schedule(cells_per_lane=2)
+    lat.set_schedule(cells_per_lane=1)
+    lat.close()
 
 
 @pytest.mark.parametrize("fused", [0, 1])

@@ -61,7 +61,8 @@ struct XchgTask {
 };
 
 // Link-mask word of a cell: bit i (1..18) set when x - e_i is a solid cell
-// (obstacle bounce-back link); bit 31 set when the cell itself is solid.
+// (obstacle bounce-back link; set for solid cells too); bit 31 set when the
+// cell itself is solid.
 constexpr uint32_t kSolidBit = 0x80000000u;
 
 struct GridGeom {

@@ -127,6 +127,21 @@ __device__ __forceinline__ void vld(const T* base, uint32_t boff, T (&out)[VEC])
   const V v = ld<V, NT>((const V*)((const char*)base + boff));
   __builtin_memcpy(out, &v, sizeof(V));
 }
+// VEC values loaded into whole 32-bit registers (a lone 16-bit value is
+// zero-extended) and split later.
+template <int BYTES> struct WideRaw { typedef typename Raw<BYTES>::V V; };
+template <> struct WideRaw<2> { typedef uint32_t V; };
+template <typename T, int VEC, bool NT>
+__device__ __forceinline__ typename WideRaw<sizeof(T) * VEC>::V ld_wide(const T* base, uint32_t boff) {
+  typedef typename Raw<sizeof(T) * VEC>::V V;
+  return (typename WideRaw<sizeof(T) * VEC>::V)ld<V, NT>((const V*)((const char*)base + boff));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void unpack_wide(typename WideRaw<sizeof(T) * VEC>::V w, T (&out)[VEC]) {
+  typedef typename Raw<sizeof(T) * VEC>::V V;
+  const V v = (V)w;
+  __builtin_memcpy(out, &v, sizeof(V));
+}
 template <typename T, int VEC, bool NT>
 __device__ __forceinline__ void vst(T* base, uint32_t boff, const T (&in)[VEC]) {
   typedef typename Raw<sizeof(T) * VEC>::V V;
@@ -189,16 +204,20 @@ __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, co
 //
 // Pull phase (branch-free, all 19 streams in flight): every population comes
 // from its source slot x - e_i -- inside the Block, from the ghost layer (the
-// neighbour Block's value), or from a bounce-back slot written by this cell in
-// the previous step (Sec. 2.1: pull scheme and half-way bounce-back).  With
-// one cell per lane the x-shifted source is a shifted load; with two, the
-// adjacent lane's value arrives by a lane shuffle.
+// neighbour Block's value), or, across a wall, from a bounce-back slot written
+// by this cell in the previous step (Sec. 2.1: pull scheme and half-way
+// bounce-back).  Across an obstacle link the cell's own f*_ibar of the
+// previous step replaces the pulled value (one more load per direction that
+// has such a link in the wave).  With one cell per lane the x-shifted source
+// is a shifted load; with two, the adjacent lane's value arrives by a lane
+// shuffle.
 //
 // Update phase: moments, BGK collision with the shifted incompressible
 // equilibrium of Eq. (2) and the Guo force term, evaluated per pair of
 // opposite directions (even part of feq and F shared, odd part flips sign);
-// aligned stores; bounce-back writes f*_ibar + 6 w_i rho0 e_i.u_w into the
-// slot of every wall/obstacle link; with FUSED the boundary values also go
+// aligned stores (zeros for solid cells, so that no cache line is written
+// in part); bounce-back writes f*_ibar + 6 w_i rho0 e_i.u_w into the slot of
+// every wall link; with FUSED the boundary values also go
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
@@ -224,6 +243,22 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   const bool xg_hi = x0 + VEC == a;         // last cell pulls e_x = -1 from the x-ghost plane
   const bool first = xl == 0;
   const bool last = (xl == xw - 1) || xg_hi;
+
+  // Link masks first (obstacle links decide which sources are replaced
+  // below); the pulls go out right behind this load.
+  uint32_t m[VEC];
+  bool solid[VEC];
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    m[k] = 0;
+    solid[k] = false;
+  }
+  if constexpr (MASK) {
+    const uint32_t* mp = A.mask + B.mask + ((long long)z * b + y) * a + x0;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) m[k] = mp[k];
+    __builtin_amdgcn_sched_barrier(0);
+  }
 
   // ---- pull phase: W[i][k] = stored value that cell k receives along e_i
   T W[kQ][VEC];
@@ -287,24 +322,36 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     }
   }
 
-  // ---- update phase
-  uint32_t m[VEC];
-  bool solid[VEC];
-  bool anysolid = false;
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) {
-    m[k] = 0;
-    solid[k] = false;
-  }
   if constexpr (MASK) {
-    const uint32_t* mp = A.mask + B.mask + ((long long)z * b + y) * a + x0;
+    // Half-way bounce-back at obstacles on the pull side: when x - e_i is
+    // solid, cell x receives its own f*_ibar of the previous step, read from
+    // its own slot of array ibar (one more load, only for directions where
+    // some lane of the wave has such a link).
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      m[k] = mp[k];
-      solid[k] = (m[k] & kSolidBit) != 0;
-      anysolid = anysolid || solid[k];
+    for (int k = 0; k < VEC; ++k) solid[k] = (m[k] & kSolidBit) != 0;
+    // All loads first, each into whole registers, and the substitutions
+    // after them: a value merged into a shared register inside its branch
+    // would make every load wait for all earlier ones.
+    typedef typename WideRaw<sizeof(T) * VEC>::V RV;
+    RV own[kQ];
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) any = any || ((m[k] >> i) & 1u);
+      if (any) own[i] = ld_wide<T, VEC, NT>(src + (rb + (long long)OPPd(i) * B.Sf), lob);
+    }
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+      T o[VEC];
+      unpack_wide<T, VEC>(own[i], o);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if ((m[k] >> i) & 1u) W[i][k] = o[k];
     }
   }
+
+  // ---- update phase
   const int gx0 = B.org[0] + x0, gy = B.org[1] + y, gz = B.org[2] + z;
   WallFlags wf;
   wf.lox = A.geo.wall[0] && gx0 == 0;
@@ -354,43 +401,48 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     ug3[k] = ph.rho0x3 * fma(ux[k], ph.g[0], fma(uy[k], ph.g[1], uz[k] * ph.g[2]));
   }
 
-  // stores of direction i for the fluid cells of the lane
+  // stores of direction i; solid cells store zero (no cell reads their
+  // slots: obstacle links are bounced on the pull side), which keeps every
+  // cache line whole (partial-line writes cost the memory a
+  // read-modify-write)
   auto store_dir = [&](int i, const T (&o)[VEC]) {
     T* base = dst + (rb + (long long)i * B.Sf);
-    if (!anysolid) {
-      vst<T, VEC, NT>(base, lob, o);
-    } else {
+    if constexpr (MASK) {
+      T v[VEC];
 #pragma unroll
-      for (int k = 0; k < VEC; ++k)
-        if (!solid[k]) sto<T, NT>(base, lob + (uint32_t)(k * sizeof(T)), o[k]);
+      for (int k = 0; k < VEC; ++k) v[k] = solid[k] ? from_c<PREC, double>(0.0) : o[k];
+      vst<T, VEC, NT>(base, lob, v);
+    } else {
+      vst<T, VEC, NT>(base, lob, o);
     }
   };
-  // bounce-back writes: cell k sends f*_q(x) to the slot (x - e_qbar, qbar)
-  // that it pulls along qbar next step when that source is a wall or solid
+  // bounce-back writes at walls: cell k sends f*_q(x) (plus the moving-wall
+  // term) to the slot (x + e_q, qbar) that it pulls along qbar next step
+  // when x + e_q lies beyond a wall: its own slot in array qbar shifted by
+  // e_q (a uniform offset from the stores' base, same lane offset), or, past
+  // an x face of the Block, the x-ghost plane (rare, kept off the common path)
   auto bounce = [&](int q, const T (&o)[VEC]) {
     const int qb = OPPd(q);
+    const int exq = EXd(q), eyq = EYd(q), ezq = EZd(q);
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       bool bb = wall_link<VEC>(wf, qb, k);
-      if constexpr (MASK) bb = (bb || ((m[k] >> qb) & 1u)) && !solid[k];
+      if constexpr (MASK) bb = bb && !solid[k];
       if (bb) {
-        const int exb = EXd(qb), eyb = EYd(qb), ezb = EZd(qb);
-        const long long row = rb + (long long)qb * B.Sf - (long long)ezb * B.Sz - (long long)eyb * B.Sx;
-        const uint32_t S1 = (uint32_t)sizeof(T);
-        // the pull phase's source slot, relative to row - 1 (recomputed here
-        // rather than held in registers through the collision)
-        uint32_t off;
-        const int j = k - exb;  // source element index relative to x0
-        const long long dxg = B.xgo + (long long)(z + 1 - ezb) * (B.Ry - B.Sz) +
-                              (long long)(y0w + 1 - eyb) * (1 - B.Sx) - seg * 64 * VEC + 1;
-        const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
-        if (j < 0) off = xg_lo ? xgb : lob;
-        else if (j >= VEC) off = xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1;
-        else off = lob + (uint32_t)(j + 1) * S1;
         T v = o[k];
         if (moving && wall_link<VEC>(wf, qb, k))
           v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(A, ph, wf, qb, k));
-        sto<T, NT>(dst + (row - 1), off, v);
+        // shifted row of array qbar, one element early so that the lane
+        // offset stays non-negative
+        const long long row = rb + (long long)qb * B.Sf + (long long)ezq * B.Sz + (long long)eyq * B.Sx;
+        const int j = k + exq;  // target element index relative to x0
+        if (!((j < 0 && xg_lo) || (j >= VEC && xg_hi))) {
+          sto<T, NT>(dst + (row - 1), lob + (uint32_t)((j + 1) * (int)sizeof(T)), v);
+        } else {
+          const long long dxg = B.xgo + (long long)(z + 1 + ezq) * (B.Ry - B.Sz) +
+                                (long long)(y0w + 1 + eyq) * (1 - B.Sx) - seg * 64 * VEC + 1;
+          sto<T, NT>(dst + (row - 1), (uint32_t)((dxg + r) * (long long)sizeof(T)), v);
+        }
       }
     }
   };
@@ -402,7 +454,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
     const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
     const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
-    return (cx | cy | cz) != 0 && !solid[k] ? 13 + cx + 3 * cy + 9 * cz : 13;
+    return (cx | cy | cz) != 0 ? 13 + cx + 3 * cy + 9 * cz : 13;
   };
   // Rows of this wave (y0w .. ylast, z fixed) off the y and z faces of the
   // Block only send from their first and last cell, to the two x-face
@@ -427,11 +479,14 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     xpf = Gp.Sf;
   }
   const uint32_t roff = (uint32_t)(r * (int)sizeof(T));
-  const bool send_lo = xm_on && x0 == 0 && !solid[0];
-  const bool send_hi = xp_on && x0 + VEC - 1 == a - 1 && !solid[VEC - 1];
+  const bool send_lo = xm_on && x0 == 0;
+  const bool send_hi = xp_on && x0 + VEC - 1 == a - 1;
+  // (solid cells send the zeros they store)
   auto xface = [&](int q, const T (&o)[VEC]) {
-    if (EXd(q) < 0 && send_lo) sto<T, false>(dst + (xm0 + (long long)q * xmf), roff, o[0]);
-    if (EXd(q) > 0 && send_hi) sto<T, false>(dst + (xp0 + (long long)q * xpf), roff, o[VEC - 1]);
+    const T zero = from_c<PREC, double>(0.0);
+    if (EXd(q) < 0 && send_lo) sto<T, false>(dst + (xm0 + (long long)q * xmf), roff, solid[0] ? zero : o[0]);
+    if (EXd(q) > 0 && send_hi)
+      sto<T, false>(dst + (xp0 + (long long)q * xpf), roff, solid[VEC - 1] ? zero : o[VEC - 1]);
   };
 
   {
@@ -568,7 +623,8 @@ __device__ __forceinline__ long long xg_off(const BlockDev& B, int i, int y, int
 // each neighbour Block straight into this Block's ghost layer (Sec. 4.3:
 // process-local communication copies from the sending to the receiving
 // Block).  One task = one (Block, neighbour offset, direction) triple.
-// Solid sources are skipped: those ghost slots hold bounce-back values.
+// Solid sources are copied too (as zeros): a cell never pulls across an
+// obstacle link (its own value replaces it), and whole lines are cheaper.
 template <typename T>
 __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const BlockDev* __restrict__ blocks,
                                                   const NbrDev* __restrict__ nbr,
@@ -592,7 +648,6 @@ __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const Bl
           gz + ez >= M.dim[2])
         continue;
       const int sx = gx + nb.tx, sy = gy + nb.ty, sz = gz + nb.tz;
-      if (mask && (mask[N.mask + ((long long)sz * N.dim[1] + sy) * N.dim[0] + sx] & kSolidBit)) continue;
       const long long so = main_off(N, i, sx, sy, sz);
       const long long o = (gx < 0 || gx >= M.dim[0]) ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz);
       grid[o] = grid[so];
@@ -635,23 +690,21 @@ __global__ void __launch_bounds__(256) k_linkmask(const uint8_t* __restrict__ so
       const int r = L / a;
       const int x = L - r * a, y = item.y0 + r, z = item.z;
       const int p[3] = {B.org[0] + x, B.org[1] + y, B.org[2] + z};
-      uint32_t m = 0;
-      if (solid[gidx(A.geo, p[0], p[1], p[2])]) {
-        m = kSolidBit;
-      } else {
-        for (int i = 1; i < kQ; ++i) {
-          const int e[3] = {EXd(i), EYd(i), EZd(i)};
-          int s[3];
-          bool wall = false;
-          for (int k = 0; k < 3; ++k) {
-            s[k] = p[k] - e[k];
-            if (s[k] < 0 || s[k] >= A.geo.n[k]) {
-              if (A.geo.wall[k]) wall = true;
-              else s[k] = (s[k] + A.geo.n[k]) % A.geo.n[k];
-            }
+      // link bits for fluid and solid cells alike (a solid cell's tell the
+      // sweep which of its slots no fluid neighbour writes)
+      uint32_t m = solid[gidx(A.geo, p[0], p[1], p[2])] ? kSolidBit : 0u;
+      for (int i = 1; i < kQ; ++i) {
+        const int e[3] = {EXd(i), EYd(i), EZd(i)};
+        int s[3];
+        bool wall = false;
+        for (int k = 0; k < 3; ++k) {
+          s[k] = p[k] - e[k];
+          if (s[k] < 0 || s[k] >= A.geo.n[k]) {
+            if (A.geo.wall[k]) wall = true;
+            else s[k] = (s[k] + A.geo.n[k]) % A.geo.n[k];
           }
-          if (!wall && solid[gidx(A.geo, s[0], s[1], s[2])]) m |= 1u << i;
         }
+        if (!wall && solid[gidx(A.geo, s[0], s[1], s[2])]) m |= 1u << i;
       }
       mask[B.mask + ((long long)z * B.dim[1] + y) * a + x] = m;
     }
@@ -659,9 +712,10 @@ __global__ void __launch_bounds__(256) k_linkmask(const uint8_t* __restrict__ so
 }
 
 // Bounce-back slots of a state loaded from outside the sweep (rest state,
-// warm start, checkpoint): for every wall or obstacle link of a fluid cell x,
-// slot (x - e_i, i) = f_ibar(x) + 6 w_i rho0 e_i.u_w, rounded as the sweep
-// rounds it (arithmetic type C).
+// warm start, checkpoint): for every wall link of a fluid cell x, slot
+// (x - e_i, i) = f_ibar(x) + 6 w_i rho0 e_i.u_w, rounded as the sweep rounds
+// it (arithmetic type C).  Obstacle links need nothing: the sweep reads the
+// cell's own f_ibar for them.
 template <int PREC, typename C>
 __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const Phys<C> ph) {
   using T = typename Stor<PREC>::T;
@@ -672,8 +726,6 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
                       A.geo.moving[5];
   for_cells(A, [&](const BlockDev& B, int x, int y, int z, bool solid) {
     if (solid) return;
-    uint32_t m = 0;
-    if (A.has_mask) m = A.mask[B.mask + ((long long)z * B.dim[1] + y) * B.dim[0] + x];
     const int gx = B.org[0] + x, gy = B.org[1] + y, gz = B.org[2] + z;
     WallFlags wf;
     wf.lox = A.geo.wall[0] && gx == 0;
@@ -683,8 +735,9 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
     wf.loz = A.geo.wall[2] && gz == 0;
     wf.hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
     for (int i = 1; i < kQ; ++i) {
+      // walls only: obstacle links are bounced on the pull side of the sweep
       const bool bw = wall_link<1>(wf, i, 0);
-      if (!bw && !((m >> i) & 1u)) continue;
+      if (!bw) continue;
       const int sx = x - EXd(i), sy = y - EYd(i), sz = z - EZd(i);
       const long long o = (sx < 0 || sx >= B.dim[0]) ? xg_off(B, i, sy, sz) : main_off(B, i, sx, sy, sz);
       T v = grid[main_off(B, OPPd(i), x, y, z)];

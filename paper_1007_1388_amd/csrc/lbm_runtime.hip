@@ -719,7 +719,9 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     }
   }
 
-  c->sched.fused_exchange = 1;
+  // measured on gfx950: the separate exchange kernel is cheaper for one
+  // Block (periodic self-copies), the fused epilogue for many small Blocks
+  c->sched.fused_exchange = nblocks > 1 ? 1 : 0;
   c->sched.item_cells = 512;
   c->sched.wg_size = 256;
   c->sched.persistent = 0;

@@ -4,8 +4,7 @@ Default workload: the force-driven plane Poiseuille channel, 256^3 cells,
 periodic in x and y, half-way bounce-back walls in z, g_x = 1e-6, tau = 0.8,
 started from rest, FP32 storage (and FP64 beside it).  One step = one sweep of
 every Block (pull, bounce-back, collision) over the whole domain plus the
-ghost-layer exchange (a separate kernel for one Block, fused into the sweep
-for several).  Median of 3 timed repeats.  Prints one JSON line.
+ghost-layer exchange.  Median of 3 timed repeats.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--seed S]
 """
@@ -150,8 +149,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--graph-steps", type=int, default=10, help="time steps per captured HIP graph")
     ap.add_argument("--fused", type=int, default=None,
-                    help="1: ghost exchange fused into the sweep, 0: separate exchange kernel "
-                         "(default: 0 for one Block, 1 for several)")
+                    help="ghost exchange: 0 copy kernel, 1 fused into the sweep, 2 x faces by the sweep and "
+                         "the rest by the copy kernel (default: the library's, 0 for one Block, 2 for several)")
     ap.add_argument("--autotune", default=None, help="autotune cache file (runs the schedule autotuner)")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run the copy probe on this many bytes (counter calibration) and exit")
@@ -170,8 +169,9 @@ def main():
     p, blocks, solid = workload(args.workload, args.seed)
     prec = args.precision
     f64m = bool(args.fp64_math) and prec in ("f32", "f64")
-    fused = args.fused if args.fused is not None else (0 if not blocks or len(blocks) == 1 else 1)
-    sched = {"graph_steps": args.graph_steps, "fused_exchange": fused}
+    sched = {"graph_steps": args.graph_steps}
+    if args.fused is not None:
+        sched["fused_exchange"] = args.fused
     r = time_gpu(p, blocks, solid, prec, f64m, args.steps, args.warmup, sched, args.autotune,
                  repeats=args.repeats)
     info = r["info"]

@@ -92,8 +92,10 @@ typedef struct lbm_ctx lbm_ctx;
 /* Kernel schedule of a context: how the Blocks are cut into work items and
  * launched (the role of the paper's per-Block kernel selection, Sec. 4.1). */
 typedef struct {
-  int32_t fused_exchange;  /* 1: the sweep writes the neighbours' ghost layers
-                              itself; 0: a separate copy kernel after the sweep */
+  int32_t fused_exchange;  /* ghost exchange: 0 = a separate copy kernel after the sweep;
+                              1 = the sweep writes every ghost value into the neighbours'
+                              ghost layers itself; 2 = the sweep writes the x-face ghost
+                              planes for rows off the y/z faces, the copy kernel the rest */
   int32_t item_cells;      /* target cells per work item (whole x-rows), >= 1 */
   int32_t wg_size;         /* threads per workgroup: 64, 128 or 256 */
   int32_t persistent;      /* 0: one workgroup per item; k > 0: k workgroups per
@@ -192,7 +194,7 @@ lbm_status lbm_get_state(lbm_ctx* c, void* f, int32_t as_fp64);
 lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64);
 
 /* The schedule in force.  After lbm_create_blocks: fused_exchange = 0 for one
- * Block and 1 for several, item_cells = 512, wg_size = 256, persistent = 0,
+ * Block and 2 for several, item_cells = 512, wg_size = 256, persistent = 0,
  * graph_steps = 0, nontemporal = 1, cells_per_lane = 0. */
 lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s);
 /* Validate and apply a schedule (rebuilds the item list and drops captured

@@ -52,11 +52,13 @@ struct ItemDev {
   int block, z, y0, nrows;
 };
 
-// Plain ghost-exchange task: ghost region of Block `dst` in offset class d,
-// one population direction i, region extent ext[3] starting at lo[3] (local
-// coordinates of dst, -1 or dim on the offset axes).
+// Plain ghost-exchange task: cells l0 .. l1-1 (x fastest) of a ghost region
+// of Block `dst` in offset class d (extent ext[3] starting at lo[3], local
+// coordinates of dst, -1 or dim on the offset axes) and the ndir population
+// directions that cross into it (5 through a face, 1 through an edge), 5 bits
+// each in dirs.
 struct XchgTask {
-  int dst, d, i, ncell;
+  int dst, d, ndir, dirs, l0, l1;
   int lo[3], ext[3];
 };
 

@@ -127,6 +127,20 @@ __device__ __forceinline__ void vld(const T* base, uint32_t boff, T (&out)[VEC])
   const V v = ld<V, NT>((const V*)((const char*)base + boff));
   __builtin_memcpy(out, &v, sizeof(V));
 }
+// One value at base + boff (bytes) by a raw buffer store: the 64-bit base
+// lives in the scalar descriptor, the lane supplies only the 32-bit offset.
+template <typename T>
+__device__ __forceinline__ void buf_store(T* base, uint32_t boff, T v) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7fffffff, 0x00020000);
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(unsigned int __attribute__((__vector_size__(8))), v),
+                                          rs, boff, 0, 0);
+  else if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, boff, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rs, boff, 0, 0);
+}
+
 // VEC values loaded into whole 32-bit registers (a lone 16-bit value is
 // zero-extended) and split later.
 template <int BYTES> struct WideRaw { typedef typename Raw<BYTES>::V V; };
@@ -220,7 +234,7 @@ __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, co
 // every wall link; with FUSED the boundary values also go
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
                                           int z, int y0w, int seg, int yend, int xw, const GhostTgt* gts) {
   using T = typename Stor<PREC>::T;
@@ -462,13 +476,18 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // with a row on a y or z face take the generic per-lane path.
   const int ylast = min(y0w + 64 / xw, yend) - 1;
   const bool yz_face = (z == 0) | (z == c - 1) | (y0w == 0) | (ylast >= b - 1);
+  constexpr bool FUSED = FX == 1;
   const bool edge = FUSED && yz_face &&
                     ((x0 == 0) | (x0 + VEC - 1 == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
   // x-ghost slot of row y for direction q: base + q * Sf (wave-uniform) plus
   // the lane's row offset within the wave
   long long xm0 = 0, xmf = 0, xp0 = 0, xpf = 0;
   bool xm_on = false, xp_on = false;
-  if (FUSED && !yz_face) {
+  // FX == 1: waves off the y/z faces (the rest takes the generic path);
+  // FX == 2: every wave, lanes whose row is off the y/z faces (the exchange
+  // kernel copies the rim rows)
+  const bool xsend = FX == 1 ? !yz_face : FX == 2;
+  if (xsend) {
     const GhostTgt& Gm = A.ghost[bid * 27 + 12];
     const GhostTgt& Gp = A.ghost[bid * 27 + 14];
     xm_on = Gm.kind != 0;
@@ -479,14 +498,15 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     xpf = Gp.Sf;
   }
   const uint32_t roff = (uint32_t)(r * (int)sizeof(T));
-  const bool send_lo = xm_on && x0 == 0;
-  const bool send_hi = xp_on && x0 + VEC - 1 == a - 1;
-  // (solid cells send the zeros they store)
+  const bool rowok = FX != 2 || (y != 0 && y != b - 1 && z != 0 && z != c - 1);
+  const bool send_lo = xm_on && x0 == 0 && rowok;
+  const bool send_hi = xp_on && x0 + VEC - 1 == a - 1 && rowok;
+  // (solid cells send the zeros they store; buffer stores keep the address
+  // in scalar registers plus the one lane offset)
   auto xface = [&](int q, const T (&o)[VEC]) {
     const T zero = from_c<PREC, double>(0.0);
-    if (EXd(q) < 0 && send_lo) sto<T, false>(dst + (xm0 + (long long)q * xmf), roff, solid[0] ? zero : o[0]);
-    if (EXd(q) > 0 && send_hi)
-      sto<T, false>(dst + (xp0 + (long long)q * xpf), roff, solid[VEC - 1] ? zero : o[VEC - 1]);
+    if (EXd(q) < 0 && send_lo) buf_store<T>(dst + (xm0 + (long long)q * xmf), roff, solid[0] ? zero : o[0]);
+    if (EXd(q) > 0 && send_hi) buf_store<T>(dst + (xp0 + (long long)q * xpf), roff, solid[VEC - 1] ? zero : o[VEC - 1]);
   };
 
   {
@@ -546,7 +566,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     store_dir(i + 1, o1);
     bounce(i, o0);
     bounce(i + 1, o1);
-    if (FUSED && !yz_face) {
+    if (xsend) {
       xface(i, o0);
       xface(i + 1, o1);
     }
@@ -583,16 +603,16 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 }
 
 // At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
 k_sweep(const SweepArgs A, const Phys<C> ph) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
   // ghost targets of the current item's Block (fused exchange)
-  __shared__ GhostTgt gts[FUSED ? 27 : 1];
+  __shared__ GhostTgt gts[FX == 1 ? 27 : 1];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const ItemDev item = A.items[it];
-    if constexpr (FUSED) {
+    if constexpr (FX == 1) {
       __syncthreads();  // the previous item's readers are done
       if (threadIdx.x < 27) gts[threadIdx.x] = A.ghost[item.block * 27 + threadIdx.x];
       __syncthreads();
@@ -609,7 +629,7 @@ k_sweep(const SweepArgs A, const Phys<C> ph) {
     const int yend = item.y0 + item.nrows;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FUSED, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw, gts);
+      sweep_row<PREC, C, MASK, FX, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw, gts);
     }
   }
 }
@@ -619,38 +639,53 @@ __device__ __forceinline__ long long xg_off(const BlockDev& B, int i, int y, int
   return B.base + (long long)i * B.Sf + B.xgo + (long long)(z + 1) * B.Ry + (y + 1);
 }
 
+// Lattice directions as tables for run-time indices (same order as EXd...).
+__constant__ int kEx[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ int kEy[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ int kEz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
 // Separate (unfused) exchange: after the sweep, copy the boundary values of
 // each neighbour Block straight into this Block's ghost layer (Sec. 4.3:
 // process-local communication copies from the sending to the receiving
-// Block).  One task = one (Block, neighbour offset, direction) triple.
-// Solid sources are copied too (as zeros): a cell never pulls across an
-// obstacle link (its own value replaces it), and whole lines are cheaper.
+// Block).  One task = one (Block, neighbour offset) pair with the directions
+// that cross.  Solid sources are copied too (as zeros): a cell never pulls
+// across an obstacle link (its own value replaces it), and whole lines are
+// cheaper.
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const BlockDev* __restrict__ blocks,
                                                   const NbrDev* __restrict__ nbr,
-                                                  const XchgTask* __restrict__ tasks, int ntasks,
-                                                  const uint32_t* __restrict__ mask) {
-  for (int task = blockIdx.y; task < ntasks; task += gridDim.y) {
+                                                  const XchgTask* __restrict__ tasks, int ntasks) {
+  // one workgroup per task; a thread copies every crossing direction of its
+  // ghost cell, all loads before the stores
+  for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
     const XchgTask t = tasks[task];
     const BlockDev M = blocks[t.dst];
     const NbrDev nb = nbr[t.dst * 27 + t.d];
     const BlockDev N = blocks[nb.id];
-    const int i = t.i;
-    const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
-    for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < t.ncell; L += gridDim.x * blockDim.x) {
+    const bool xplane = t.lo[0] < 0 || t.lo[0] >= M.dim[0];
+    for (int L = t.l0 + threadIdx.x; L < t.l1; L += blockDim.x) {
       const int q0 = L % t.ext[0];
       const int r = L / t.ext[0];
       const int q1 = r % t.ext[1];
       const int q2 = r / t.ext[1];
       const int gx = t.lo[0] + q0, gy = t.lo[1] + q1, gz = t.lo[2] + q2;
-      // only slots whose puller (g + e_i) lies inside the receiving Block
-      if (gx + ex < 0 || gx + ex >= M.dim[0] || gy + ey < 0 || gy + ey >= M.dim[1] || gz + ez < 0 ||
-          gz + ez >= M.dim[2])
-        continue;
       const int sx = gx + nb.tx, sy = gy + nb.ty, sz = gz + nb.tz;
-      const long long so = main_off(N, i, sx, sy, sz);
-      const long long o = (gx < 0 || gx >= M.dim[0]) ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz);
-      grid[o] = grid[so];
+      T v[5];
+      bool ok[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int i = (t.dirs >> (5 * j)) & 31;
+        // only slots whose puller (g + e_i) lies inside the receiving Block
+        ok[j] = j < t.ndir && gx + kEx[i] >= 0 && gx + kEx[i] < M.dim[0] && gy + kEy[i] >= 0 &&
+                gy + kEy[i] < M.dim[1] && gz + kEz[i] >= 0 && gz + kEz[i] < M.dim[2];
+        if (ok[j]) v[j] = grid[main_off(N, i, sx, sy, sz)];
+      }
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int i = (t.dirs >> (5 * j)) & 31;
+        if (ok[j]) grid[xplane ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz)] = v[j];
+      }
     }
   }
 }
@@ -922,56 +957,57 @@ __global__ void __launch_bounds__(256) k_copy16(const u32x4* __restrict__ src, u
 // ------------------------------------------------------------- launchers
 using SweepFn = void (*)(SweepArgs, Phys<double>, Phys<float>, dim3, dim3, hipStream_t);
 
-template <int PREC, typename C, bool MASK, bool FUSED, bool NT, int VEC>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
 static void launch_sweep_t(SweepArgs a, Phys<double> pd, Phys<float> pf, dim3 g, dim3 b, hipStream_t s) {
   if constexpr (sizeof(C) == 8)
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT, VEC>), g, b, 0, s, a, pd);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC>), g, b, 0, s, a, pd);
   else
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FUSED, NT, VEC>), g, b, 0, s, a, pf);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC>), g, b, 0, s, a, pf);
 }
 
 template <int PREC, typename C, int VEC>
-static SweepFn pick3(bool mask, bool fused, bool nt) {
+static SweepFn pick3(bool mask, int fx, bool nt) {
+#define LBM_PICK(M, F) \
+  return nt ? launch_sweep_t<PREC, C, M, F, true, VEC> : launch_sweep_t<PREC, C, M, F, false, VEC>
   if (mask) {
-    if (fused) return nt ? launch_sweep_t<PREC, C, true, true, true, VEC> : launch_sweep_t<PREC, C, true, true, false, VEC>;
-    return nt ? launch_sweep_t<PREC, C, true, false, true, VEC> : launch_sweep_t<PREC, C, true, false, false, VEC>;
+    if (fx == 1) LBM_PICK(true, 1);
+    if (fx == 2) LBM_PICK(true, 2);
+    LBM_PICK(true, 0);
   }
-  if (fused) return nt ? launch_sweep_t<PREC, C, false, true, true, VEC> : launch_sweep_t<PREC, C, false, true, false, VEC>;
-  return nt ? launch_sweep_t<PREC, C, false, false, true, VEC> : launch_sweep_t<PREC, C, false, false, false, VEC>;
+  if (fx == 1) LBM_PICK(false, 1);
+  if (fx == 2) LBM_PICK(false, 2);
+  LBM_PICK(false, 0);
+#undef LBM_PICK
 }
 
 // Storage modes with a two-cells-per-lane sweep: 16-bit storage (four bytes
 // per lane and stream, like FP32) and FP32 storage with FP64 arithmetic.
 bool sweep_vec2_ok(int prec, bool f64math) { return prec >= 2 || (prec == 1 && f64math); }
 
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, int vec, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
   const bool v = vec == 2 && sweep_vec2_ok(prec, f64math);
   switch (prec) {
-    case 0: fn = pick3<0, double, 1>(mask, fused, nt); break;
+    case 0: fn = pick3<0, double, 1>(mask, fx, nt); break;
     case 1:
-      if (f64math) fn = v ? pick3<1, double, 2>(mask, fused, nt) : pick3<1, double, 1>(mask, fused, nt);
-      else fn = pick3<1, float, 1>(mask, fused, nt);
+      if (f64math) fn = v ? pick3<1, double, 2>(mask, fx, nt) : pick3<1, double, 1>(mask, fx, nt);
+      else fn = pick3<1, float, 1>(mask, fx, nt);
       break;
-    case 2: fn = v ? pick3<2, float, 2>(mask, fused, nt) : pick3<2, float, 1>(mask, fused, nt); break;
-    default: fn = v ? pick3<3, float, 2>(mask, fused, nt) : pick3<3, float, 1>(mask, fused, nt); break;
+    case 2: fn = v ? pick3<2, float, 2>(mask, fx, nt) : pick3<2, float, 1>(mask, fx, nt); break;
+    default: fn = v ? pick3<3, float, 2>(mask, fx, nt) : pick3<3, float, 1>(mask, fx, nt); break;
   }
   fn(a, pd, pf, grid, block, s);
 }
 
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
-                     int ntasks, int max_cells, const uint32_t* mask, hipStream_t s) {
+                     int ntasks, hipStream_t s) {
   if (ntasks <= 0) return;
-  const int per = 256;
-  int gx = (max_cells + per - 1) / per;
-  if (gx > 64) gx = 64;
-  if (gx < 1) gx = 1;
-  dim3 g(gx, ntasks < 65535 ? ntasks : 65535), b(per);
+  dim3 g(ntasks < (1 << 20) ? ntasks : (1 << 20)), b(256);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks, mask); break;
-    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks, mask); break;
-    default: hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks, mask); break;
+    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks); break;
+    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks); break;
+    default: hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks); break;
   }
 }
 

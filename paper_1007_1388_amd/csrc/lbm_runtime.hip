@@ -23,11 +23,11 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-void launch_sweep(int prec, bool f64math, bool mask, bool fused, bool nt, int vec, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
 bool sweep_vec2_ok(int prec, bool f64math);
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
-                     int ntasks, int max_cells, const uint32_t* mask, hipStream_t s);
+                     int ntasks, hipStream_t s);
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
                    const Phys<float>& pf, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
@@ -92,8 +92,8 @@ struct lbm_ctx {
   std::vector<BlockDev> bh;
   std::vector<NbrDev> nbh;
   std::vector<ItemDev> items_h;
-  std::vector<XchgTask> tasks_h;
-  int xchg_max_cells = 0;
+  std::vector<XchgTask> tasks_h;   // every ghost slot
+  std::vector<XchgTask> rim_h;     // the same, x faces cut to the rows on y/z faces
   GridGeom geo{};
   Phys<double> phd{};
   Phys<float> phf{};
@@ -109,6 +109,7 @@ struct lbm_ctx {
   ItemDev* d_items = nullptr;
   size_t items_cap = 0;
   XchgTask* d_tasks = nullptr;
+  XchgTask* d_rim = nullptr;
   uint32_t* d_mask = nullptr;
   bool has_mask = false;
   bool x_even = false;   // every Block's x extent is even (two cells per lane possible)
@@ -263,9 +264,25 @@ lbm_status upload_items(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// Exchange tasks: per (Block, neighbour offset) the directions that cross,
+// cut into chunks of at most kXchgChunk cells (one workgroup each).  The rim
+// list serves the schedule whose sweep writes the x-face ghost planes of rows
+// off the sender's y and z faces itself (fused_exchange = 2): its x-face
+// tasks keep only the rows y = 0, b-1 and the planes z = 0, c-1 (x
+// neighbours share their y and z extents in a Cartesian tiling).
+constexpr int kXchgChunk = 1024;
+
+void push_chunks(std::vector<XchgTask>& out, XchgTask t, int ncell) {
+  for (int l0 = 0; l0 < ncell; l0 += kXchgChunk) {
+    t.l0 = l0;
+    t.l1 = std::min(ncell, l0 + kXchgChunk);
+    out.push_back(t);
+  }
+}
+
 void build_tasks(lbm_ctx* c) {
   c->tasks_h.clear();
-  c->xchg_max_cells = 0;
+  c->rim_h.clear();
   for (int j = 0; j < (int)c->bh.size(); ++j) {
     const BlockDev& M = c->bh[j];
     for (int d = 0; d < 27; ++d) {
@@ -274,11 +291,11 @@ void build_tasks(lbm_ctx* c) {
       XchgTask t{};
       t.dst = j;
       t.d = d;
-      t.ncell = 1;
+      int ncell = 1;
       for (int k = 0; k < 3; ++k) {
         t.lo[k] = off[k] < 0 ? -1 : (off[k] > 0 ? M.dim[k] : 0);
         t.ext[k] = off[k] == 0 ? M.dim[k] : 1;
-        t.ncell *= t.ext[k];
+        ncell *= t.ext[k];
       }
       for (int i = 1; i < kQ; ++i) {
         bool ok = true, any = false;
@@ -288,12 +305,29 @@ void build_tasks(lbm_ctx* c) {
             if (E3[i][k] != -off[k]) ok = false;
           }
         }
-        if (ok && any) {
-          t.i = i;
-          c->tasks_h.push_back(t);
-          c->xchg_max_cells = std::max(c->xchg_max_cells, t.ncell);
-        }
+        if (ok && any) t.dirs |= i << (5 * t.ndir++);
       }
+      if (t.ndir == 0) continue;
+      push_chunks(c->tasks_h, t, ncell);
+      const bool xface = off[0] != 0 && off[1] == 0 && off[2] == 0;
+      if (!xface) {
+        push_chunks(c->rim_h, t, ncell);
+        continue;
+      }
+      const int b = M.dim[1], cz = M.dim[2];
+      auto part = [&](int y0, int ny, int z0, int nz) {
+        if (ny <= 0 || nz <= 0) return;
+        XchgTask r = t;
+        r.lo[1] = y0;
+        r.ext[1] = ny;
+        r.lo[2] = z0;
+        r.ext[2] = nz;
+        push_chunks(c->rim_h, r, ny * nz);
+      };
+      part(0, b, 0, 1);                     // z = 0
+      if (cz > 1) part(0, b, cz - 1, 1);    // z = c - 1
+      part(0, 1, 1, cz - 2);                // y = 0, 0 < z < c - 1
+      if (b > 1) part(b - 1, 1, 1, cz - 2); // y = b - 1
     }
   }
 }
@@ -337,9 +371,11 @@ std::vector<GhostTgt> build_ghost_table(const lbm_ctx* c) {
   return t;
 }
 
-void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s) {
-  launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_tasks, (int)c->tasks_h.size(),
-                  c->xchg_max_cells, c->has_mask ? c->d_mask : nullptr, s);
+void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s, bool rim = false) {
+  if (rim)
+    launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_rim, (int)c->rim_h.size(), s);
+  else
+    launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_tasks, (int)c->tasks_h.size(), s);
 }
 
 // Ghost layers and bounce-back slots of a state written from outside the sweep.
@@ -362,13 +398,13 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   int grid = nitems;
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
-  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange != 0, c->sched.nontemporal != 0,
+  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange, c->sched.nontemporal != 0,
                cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
   enqueue_sweep(c, from, s);
-  if (!c->sched.fused_exchange) enqueue_exchange(c, 1 - from, s);
+  if (c->sched.fused_exchange != 1) enqueue_exchange(c, 1 - from, s, c->sched.fused_exchange == 2);
 }
 
 lbm_status capture(lbm_ctx* c, int from, int nsteps, hipGraphExec_t* out) {
@@ -497,6 +533,10 @@ bool sched_valid(const lbm_schedule& s, std::string& err) {
   }
   if (s.persistent < 0 || s.persistent > 64 || s.graph_steps < 0 || s.graph_steps > 4096) {
     err = "persistent or graph_steps out of range";
+    return false;
+  }
+  if (s.fused_exchange < 0 || s.fused_exchange > 2) {
+    err = "fused_exchange must be 0, 1 or 2";
     return false;
   }
   if (s.cells_per_lane < 0 || s.cells_per_lane > 2) {
@@ -719,9 +759,11 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     }
   }
 
-  // measured on gfx950: the separate exchange kernel is cheaper for one
-  // Block (periodic self-copies), the fused epilogue for many small Blocks
-  c->sched.fused_exchange = nblocks > 1 ? 1 : 0;
+  // measured on gfx950: one Block exchanges cheapest with the copy kernel
+  // alone; several Blocks with the x faces written by the sweep (mode 2),
+  // whose rim leaves the copy kernel contiguous rows.  The fully fused
+  // epilogue (mode 1) holds the sweep to fewer resident waves.
+  c->sched.fused_exchange = nblocks > 1 ? 2 : 0;
   c->sched.item_cells = 512;
   c->sched.wg_size = 256;
   c->sched.persistent = 0;
@@ -742,17 +784,20 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->d_nbr = (NbrDev*)dalloc(c, sizeof(NbrDev) * c->nbh.size());
   c->d_ghost = (GhostTgt*)dalloc(c, sizeof(GhostTgt) * c->nbh.size());
   c->d_tasks = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->tasks_h.size()));
+  c->d_rim = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->rim_h.size()));
   c->d_partial = (double*)dalloc(c, sizeof(double) * 6 * c->nparts);
   c->d_red = (double*)dalloc(c, sizeof(double) * 8);
-  if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_partial ||
-      !c->d_red)
+  if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_rim ||
+      !c->d_partial || !c->d_red)
     return bail(LBM_ENOMEM, "device allocation failed");
   if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_ghost, build_ghost_table(c).data(), sizeof(GhostTgt) * c->nbh.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       (!c->tasks_h.empty() && hipMemcpy(c->d_tasks, c->tasks_h.data(), sizeof(XchgTask) * c->tasks_h.size(),
-                                        hipMemcpyHostToDevice) != hipSuccess))
+                                        hipMemcpyHostToDevice) != hipSuccess) ||
+      (!c->rim_h.empty() && hipMemcpy(c->d_rim, c->rim_h.data(), sizeof(XchgTask) * c->rim_h.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess))
     return bail(LBM_EDEVICE, "upload of block tables failed");
   if (upload_items(c) != LBM_OK) return bail(LBM_ENOMEM, "item list upload failed");
   if (zero_grids(c) != LBM_OK) return bail(LBM_EDEVICE, "grid initialisation failed");
@@ -837,7 +882,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms) {
   if (!c || !sweep_ms || !exchange_ms) return fail(LBM_EINVAL, "NULL argument");
   if (n < 1 || n > 100000) return fail(LBM_EINVAL, "step count must be in [1, 100000]");
-  const bool ex = !c->sched.fused_exchange;
+  const bool ex = c->sched.fused_exchange != 1;
   const size_t ne = (size_t)n * (ex ? 3 : 2);
   std::vector<hipEvent_t> ev(ne, nullptr);
   lbm_status st = LBM_OK;
@@ -851,7 +896,7 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* excha
       enqueue_sweep(c, c->cur, c->stream);
       (void)hipEventRecord(ev[k++], c->stream);
       if (ex) {
-        enqueue_exchange(c, 1 - c->cur, c->stream);
+        enqueue_exchange(c, 1 - c->cur, c->stream, c->sched.fused_exchange == 2);
         (void)hipEventRecord(ev[k++], c->stream);
       }
       c->cur = 1 - c->cur;
@@ -1094,7 +1139,8 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
   for (int pass = 0; pass < 2 && st == LBM_OK; ++pass) {
     for (int knob = 0; knob < 6 && st == LBM_OK; ++knob) {
       std::vector<lbm_schedule> cand;
-      for (size_t q = 0; q < (knob == 0 ? cells.size() : knob == 1 ? wgs.size() : knob == 2 ? pers.size() : 2);
+      for (size_t q = 0;
+           q < (knob == 0 ? cells.size() : knob == 1 ? wgs.size() : knob == 2 ? pers.size() : knob == 4 ? 3 : 2);
            ++q) {
         lbm_schedule s = best;
         if (knob == 0) s.item_cells = cells[q];

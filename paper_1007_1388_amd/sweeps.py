@@ -8,9 +8,10 @@ size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
         the single-Block scaling study of Sec. 5.1.
 blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
         the 512x256x256 porous channel as its uneven Blocks; per-launch times
-        of the sweep and of the separate ghost exchange (HIP events), and the
-        step time with the exchange fused into the sweep: the cost of Blocks
-        and of their on-GPU copies, Sec. 5.2.
+        of the sweep and of the separate ghost exchange (HIP events) for the
+        three exchange schedules (0 copy kernel, 2 x faces written by the
+        sweep, 1 fully fused): the cost of Blocks and of their on-GPU copies,
+        Sec. 5.2.
 
 Prints one JSON line per case.
 """
@@ -67,14 +68,14 @@ def block_sweep(steps):
     n = 384
     for k in (1, 2, 3, 4, 6):
         blocks = inputs.uniform_blocks((n, n, n), (k, k, k))
-        for fused in (0, 1):
+        for fused in (0, 2, 1):
             r = measure((n, n, n), "f32", steps, blocks=blocks, fused=fused)
             print(json.dumps(dict(study="blocks", domain="384^3 periodic", split="%dx%dx%d" % (k, k, k),
                                   precision="f32", fused=fused, **r)), flush=True)
     p = inputs.preset("porous512")
     blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
     solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
-    for fused in (0, 1):
+    for fused in (0, 2, 1):
         r = measure(p["dims"], "f32", steps, blocks=blocks, solid=solid, walls=p["walls"], tau=p["tau"],
                     force=p["force"], fused=fused)
         print(json.dumps(dict(study="blocks", domain="porous 512x256x256", split="uneven {32,48,64}",

@@ -91,6 +91,7 @@ def test_porous512_full_partition_invariance_and_windows():
     steps = 12
     a = gpu_lattice(p, blocks=blocks, precision="f32")
     a.set_geometry(solid)
+    a.set_schedule(fused_exchange=2)  # x faces written by the sweep, the rest by the copy kernel
     a.step(steps)
     fa = a.get_state(as_fp64=False)
     ra, ua = a.macroscopic()

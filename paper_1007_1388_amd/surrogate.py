@@ -322,6 +322,20 @@ class UNet:
         for l in self.layers:
             l.adam(self.t, lr, stream=stream)
 
+    def io(self):
+        """(name, layer, input, output) of every convolution, forward order."""
+        return [("e0a", self.e0a, self.x, self.a0), ("e0b", self.e0b, self.a0, self.skip0),
+                ("dn0", self.dn0, self.skip0, self.l1in), ("e1a", self.e1a, self.l1in, self.a1),
+                ("e1b", self.e1b, self.a1, self.skip1), ("dn1", self.dn1, self.skip1, self.l2in),
+                ("e2a", self.e2a, self.l2in, self.a2), ("e2b", self.e2b, self.a2, self.skip2),
+                ("dn2", self.dn2, self.skip2, self.l3in), ("e3a", self.e3a, self.l3in, self.a3),
+                ("e3b", self.e3b, self.a3, self.b3), ("up2", self.up2, self.u2, self.upc2),
+                ("d2a", self.d2a, self.cat2, self.d2), ("d2b", self.d2b, self.d2, self.d2o),
+                ("up1", self.up1, self.u1, self.upc1), ("d1a", self.d1a, self.cat1, self.d1),
+                ("d1b", self.d1b, self.d1, self.d1o), ("up0", self.up0, self.u0, self.upc0),
+                ("d0a", self.d0a, self.cat0, self.d0), ("d0b", self.d0b, self.d0, self.d0o),
+                ("head", self.head, self.d0o, self.pred)]
+
     def flops_forward(self):
         n, D, H, W = self.n, self.D, self.H, self.W
         v = [n * D * H * W // (8 ** k) for k in range(4)]
@@ -329,3 +343,53 @@ class UNet:
               self.e2b: 2, self.dn2: 3, self.e3a: 3, self.e3b: 3, self.up2: 2, self.d2a: 2, self.d2b: 2,
               self.up1: 1, self.d1a: 1, self.d1b: 1, self.up0: 0, self.d0a: 0, self.d0b: 0, self.head: 0}
         return sum(l.flops(v[lv[l]]) for l in self.layers)
+
+
+def bench_layers(n=8, D=128, H=64, W=64, reps=5, log=print):
+    """Per-layer times of the three convolution kernels at the given shape
+    (HIP events on the current stream); returns a list of dicts with
+    TFLOP/s (2 * voxels * taps * Cin * Cout per kernel)."""
+    import torch
+    net = UNet(n, D, H, W, seed=1)
+    net.forward()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    L = lib()
+    rows = []
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for name, l, x, y in net.io():
+        dx = Act(x.n, x.d, x.h, x.w, x.c)
+        fl = l.flops(y.n * y.d * y.h * y.w)
+        t_f = timed(lambda: l.forward(x, y))
+        t_d = timed(lambda: _ck(L.lbm_conv3d_bwd_data(y.ref, l.wt.data_ptr(), dx.ref, None, l.k, l.stride, 0, None),
+                                "lbm_conv3d_bwd_data"))
+        t_w = timed(lambda: _ck(L.lbm_conv3d_bwd_weight(x.ref, y.ref, l.gw.data_ptr(), l.gb.data_ptr(), l.k, l.stride,
+                                                        None), "lbm_conv3d_bwd_weight"))
+        r = dict(layer=name, cin=l.cin, cout=l.cout, k=l.k, stride=l.stride, out=(y.d, y.h, y.w), gflop=fl / 1e9,
+                 fwd_ms=t_f, bwd_data_ms=t_d, bwd_weight_ms=t_w, fwd_tflops=fl / t_f / 1e9,
+                 bwd_data_tflops=fl / t_d / 1e9, bwd_weight_tflops=fl / t_w / 1e9)
+        rows.append(r)
+        log(r)
+        del dx
+    tot = sum(r["gflop"] for r in rows)
+    for kind in ("fwd", "bwd_data", "bwd_weight"):
+        t = sum(r[kind + "_ms"] for r in rows)
+        log(dict(total=kind, gflop=tot, ms=t, tflops=tot / t))
+    return rows
+
+
+if __name__ == "__main__":
+    import json
+    import torch
+    torch.cuda.init()
+    bench_layers(log=lambda r: print(json.dumps(r), flush=True))

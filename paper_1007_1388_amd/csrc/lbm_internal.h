@@ -36,7 +36,11 @@ struct BlockDev {
   long long xgo;    // offset of a population's x-ghost plane from the array start
   long long base;   // element offset of main[0][z=-1][y=-1][x=0]
   long long mask;   // offset of the Block's link masks (a*b*c words), -1: none
-  long long pad1;
+  int wrap;         // bit k (x = 1, y = 2, z = 4): the Block is its own neighbour
+                    // across both faces of axis k (periodic, one Block along k);
+                    // the sweep then reads across that axis from the Block itself
+                    // and no ghost value on that axis is used
+  int pad1;
 };
 
 // Neighbour entry of a Block for offset class d = 13 + dx + 3 dy + 9 dz:

@@ -250,9 +250,18 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // neighbour lane of its own live row.
   if (x0 >= a || y >= yend) return;
 
-  const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx + seg * 64 * VEC;
-  const uint32_t lo = (uint32_t)(r * B.Sx + xl * VEC);
+  // Scalar bases address row starts; the lane offset carries the row within
+  // the wave, the segment and the lane's cells (all non-negative).
+  const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx;
+  const uint32_t lo = (uint32_t)(r * B.Sx + x0);
   const uint32_t lob = lo * (uint32_t)sizeof(T);
+  // axes on which the Block wraps onto itself (uniform; y only with one row
+  // per wave, so y0w is every live lane's row)
+  const bool wx = (B.wrap & 1) != 0, wy = (B.wrap & 2) != 0, wz = (B.wrap & 4) != 0;
+  auto wrapc = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  // in-row sources past the x faces of a Block that wraps in x
+  const uint32_t xwrap_lo = (uint32_t)((r * B.Sx + a) * (int)sizeof(T));  // x = -1 -> a - 1
+  const uint32_t xwrap_hi = (uint32_t)((r * B.Sx + 1) * (int)sizeof(T));  // x = a  -> 0
   const bool xg_lo = x0 == 0;              // first cell pulls e_x = +1 from the x-ghost plane
   const bool xg_hi = x0 + VEC == a;         // last cell pulls e_x = -1 from the x-ghost plane
   const bool first = xl == 0;
@@ -280,29 +289,32 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
-    // source row of direction i, x-aligned
-    const long long row = rb + (long long)i * B.Sf - (long long)ez * B.Sz - (long long)ey * B.Sx;
+    // source row of direction i (wrapped on the Block's wrap axes)
+    const int zs = wz ? wrapc(z - ez, c) : z - ez;
+    const int ys = wy ? wrapc(y0w - ey, b) : y0w - ey;
+    const long long row = B.base + (long long)i * B.Sf + (long long)(zs + 1) * B.Sz + (long long)(ys + 1) * B.Sx;
     // Scalar base one element before the row so that every lane offset is
-    // non-negative (x - 1 of a segment's first lane); the x-ghost slot of the
-    // lane's source row, relative to the same base:
+    // non-negative (x - 1 of the first cell); the x-ghost slot of the lane's
+    // source row, relative to the same base:
     const T* pr = src + (row - 1);
-    const long long dxg = B.xgo + (long long)(z + 1 - ez) * (B.Ry - B.Sz) +
-                          (long long)(y0w + 1 - ey) * (1 - B.Sx) - seg * 64 * VEC + 1;
+    const long long dxg = B.xgo + (long long)(zs + 1) * (B.Ry - B.Sz) + (long long)(ys + 1) * (1 - B.Sx) + 1;
     const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
+    const uint32_t xlo = wx ? xwrap_lo : xgb, xhi = wx ? xwrap_hi : xgb;
     const uint32_t S1 = (uint32_t)sizeof(T);
     if constexpr (VEC == 1) {
       uint32_t off = lob + (uint32_t)((1 - ex) * (int)sizeof(T));
-      if (ex > 0) off = xg_lo ? xgb : off;
-      if (ex < 0) off = xg_hi ? xgb : off;
+      if (ex > 0) off = xg_lo ? xlo : off;
+      if (ex < 0) off = xg_hi ? xhi : off;
       W[i][0] = ldo<T, NT>(pr, off);
     } else {
       T V[VEC];
       vld<T, VEC, NT>(pr, lob + S1, V);
-      // the element just outside the vector: x-ghost slot, neighbouring
-      // segment, or (interior lanes, replaced by the shuffle) the lane's own
+      // the element just outside the vector: x-ghost slot (or, wrapping, the
+      // other end of the row), neighbouring segment, or (interior lanes,
+      // replaced by the shuffle) the lane's own
       uint32_t off = lob + S1;
-      if (ex > 0) off = first ? (xg_lo ? xgb : lob) : lob + S1;
-      if (ex < 0) off = last ? (xg_hi ? xgb : lob + (uint32_t)(VEC + 1) * S1) : lob + S1;
+      if (ex > 0) off = first ? (xg_lo ? xlo : lob) : lob + S1;
+      if (ex < 0) off = last ? (xg_hi ? xhi : lob + (uint32_t)(VEC + 1) * S1) : lob + S1;
       T e = V[0];
       if (ex != 0) e = ldo<T, NT>(pr, off);
 #pragma unroll
@@ -446,15 +458,18 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
         T v = o[k];
         if (moving && wall_link<VEC>(wf, qb, k))
           v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(A, ph, wf, qb, k));
-        // shifted row of array qbar, one element early so that the lane
-        // offset stays non-negative
-        const long long row = rb + (long long)qb * B.Sf + (long long)ezq * B.Sz + (long long)eyq * B.Sx;
+        // shifted row of array qbar (wrapped like the pull that reads it),
+        // one element early so that the lane offset stays non-negative
+        const int zt = wz ? wrapc(z + ezq, c) : z + ezq;
+        const int yt = wy ? wrapc(y0w + eyq, b) : y0w + eyq;
+        const long long row = B.base + (long long)qb * B.Sf + (long long)(zt + 1) * B.Sz + (long long)(yt + 1) * B.Sx;
         const int j = k + exq;  // target element index relative to x0
         if (!((j < 0 && xg_lo) || (j >= VEC && xg_hi))) {
           sto<T, NT>(dst + (row - 1), lob + (uint32_t)((j + 1) * (int)sizeof(T)), v);
+        } else if (wx) {
+          sto<T, NT>(dst + (row - 1), j < 0 ? xwrap_lo : xwrap_hi, v);
         } else {
-          const long long dxg = B.xgo + (long long)(z + 1 + ezq) * (B.Ry - B.Sz) +
-                                (long long)(y0w + 1 + eyq) * (1 - B.Sx) - seg * 64 * VEC + 1;
+          const long long dxg = B.xgo + (long long)(zt + 1) * (B.Ry - B.Sz) + (long long)(yt + 1) * (1 - B.Sx) + 1;
           sto<T, NT>(dst + (row - 1), (uint32_t)((dxg + r) * (long long)sizeof(T)), v);
         }
       }
@@ -465,9 +480,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   auto nbr_of = [&](int q, int k) {
     const int x = x0 + k;
     const int qx = EXd(q), qy = EYd(q), qz = EZd(q);
-    const int cx = (qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0);
-    const int cy = (qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0);
-    const int cz = (qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0);
+    // (crossing an axis the Block wraps on is no crossing)
+    const int cx = wx ? 0 : ((qx > 0 && x == a - 1) ? 1 : ((qx < 0 && x == 0) ? -1 : 0));
+    const int cy = wy ? 0 : ((qy > 0 && y == b - 1) ? 1 : ((qy < 0 && y == 0) ? -1 : 0));
+    const int cz = wz ? 0 : ((qz > 0 && z == c - 1) ? 1 : ((qz < 0 && z == 0) ? -1 : 0));
     return (cx | cy | cz) != 0 ? 13 + cx + 3 * cy + 9 * cz : 13;
   };
   // Rows of this wave (y0w .. ylast, z fixed) off the y and z faces of the
@@ -676,9 +692,13 @@ __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const Bl
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
         const int i = (t.dirs >> (5 * j)) & 31;
-        // only slots whose puller (g + e_i) lies inside the receiving Block
-        ok[j] = j < t.ndir && gx + kEx[i] >= 0 && gx + kEx[i] < M.dim[0] && gy + kEy[i] >= 0 &&
-                gy + kEy[i] < M.dim[1] && gz + kEz[i] >= 0 && gz + kEz[i] < M.dim[2];
+        // only slots whose puller (g + e_i, folded on the axes the Block
+        // wraps on) lies inside the receiving Block
+        int px = gx + kEx[i], py = gy + kEy[i], pz = gz + kEz[i];
+        if (M.wrap & 1) px = px < 0 ? px + M.dim[0] : (px >= M.dim[0] ? px - M.dim[0] : px);
+        if (M.wrap & 2) py = py < 0 ? py + M.dim[1] : (py >= M.dim[1] ? py - M.dim[1] : py);
+        if (M.wrap & 4) pz = pz < 0 ? pz + M.dim[2] : (pz >= M.dim[2] ? pz - M.dim[2] : pz);
+        ok[j] = j < t.ndir && px >= 0 && px < M.dim[0] && py >= 0 && py < M.dim[1] && pz >= 0 && pz < M.dim[2];
         if (ok[j]) v[j] = grid[main_off(N, i, sx, sy, sz)];
       }
 #pragma unroll
@@ -773,7 +793,11 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
       // walls only: obstacle links are bounced on the pull side of the sweep
       const bool bw = wall_link<1>(wf, i, 0);
       if (!bw) continue;
-      const int sx = x - EXd(i), sy = y - EYd(i), sz = z - EZd(i);
+      // the slot the sweep pulls from (wrapped on the Block's wrap axes)
+      int sx = x - EXd(i), sy = y - EYd(i), sz = z - EZd(i);
+      if (B.wrap & 1) sx = sx < 0 ? sx + B.dim[0] : (sx >= B.dim[0] ? sx - B.dim[0] : sx);
+      if (B.wrap & 2) sy = sy < 0 ? sy + B.dim[1] : (sy >= B.dim[1] ? sy - B.dim[1] : sy);
+      if (B.wrap & 4) sz = sz < 0 ? sz + B.dim[2] : (sz >= B.dim[2] ? sz - B.dim[2] : sz);
       const long long o = (sx < 0 || sx >= B.dim[0]) ? xg_off(B, i, sy, sz) : main_off(B, i, sx, sy, sz);
       T v = grid[main_off(B, OPPd(i), x, y, z)];
       if (moving && bw) v = from_c<PREC, C>(to_c<PREC, C>(v) + wall_corr<C, 1>(sa, ph, wf, i, 0));

@@ -288,6 +288,9 @@ void build_tasks(lbm_ctx* c) {
     for (int d = 0; d < 27; ++d) {
       if (d == 13 || c->nbh[(size_t)j * 27 + d].id < 0) continue;
       const int off[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+      // ghost slots across an axis the Block wraps on are never read
+      if (((off[0] != 0) && (M.wrap & 1)) || ((off[1] != 0) && (M.wrap & 2)) || ((off[2] != 0) && (M.wrap & 4)))
+        continue;
       XchgTask t{};
       t.dst = j;
       t.d = d;
@@ -367,6 +370,9 @@ std::vector<GhostTgt> build_ghost_table(const lbm_ctx* c) {
       g.main0 = M.base + (long long)(n.tz + 1) * M.Sz + (long long)(n.ty + 1) * M.Sx + n.tx;
       g.xg0 = M.base + M.xgo + (long long)(n.tz + 1) * M.Ry + (n.ty + 1);
       g.kind = cx == 0 ? 1 : 2;
+      // the receiver never reads ghost slots across an axis it wraps on
+      const int cy = (d / 3) % 3 - 1, cz = d / 9 - 1;
+      if ((cx != 0 && (M.wrap & 1)) || (cy != 0 && (M.wrap & 2)) || (cz != 0 && (M.wrap & 4))) g.kind = 0;
     }
   return t;
 }
@@ -756,6 +762,20 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       nb.tx = (q[0] - blocks[m].lo[0] - off3[0]) - (rep[0] - blocks[j].lo[0]);
       nb.ty = (q[1] - blocks[m].lo[1] - off3[1]) - (rep[1] - blocks[j].lo[1]);
       nb.tz = (q[2] - blocks[m].lo[2] - off3[2]) - (rep[2] - blocks[j].lo[2]);
+    }
+  }
+
+  // Axes on which a Block is its own neighbour across both faces: the sweep
+  // reads across them from the Block itself (no ghost values, no copies).
+  // y only where every wave holds one row of the Block (x extent > 64 also
+  // with two cells per lane), so that the wrap is uniform per wave.
+  for (int j = 0; j < nblocks; ++j) {
+    BlockDev& B = c->bh[j];
+    B.wrap = 0;
+    const int st[3] = {1, 3, 9};
+    for (int k = 0; k < 3; ++k) {
+      const bool self = c->nbh[(size_t)j * 27 + 13 - st[k]].id == j && c->nbh[(size_t)j * 27 + 13 + st[k]].id == j;
+      if (self && (k != 1 || B.dim[0] > 64)) B.wrap |= 1 << k;
     }
   }
 

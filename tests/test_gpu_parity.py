@@ -157,6 +157,33 @@ def test_partition_invariance_bitwise(precision, tiling, dims):
     assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_self_wrapping_block_matches_tiling(precision):
+    """A Block that is its own neighbour along x and y (x extent > 64) reads
+    across those axes from itself instead of its ghost layers: bitwise equal
+    to tilings that exchange, with obstacles straddling the periodic faces and
+    walls in z."""
+    dims = (80, 12, 10)
+    solid = inputs.porous_spheres(dims, target_fraction=0.12, radius=(1, 3), seed=5)
+    case = channel(dims=dims, solid=solid, force=(1e-5, 3e-6, 0.0), tau=0.75, seed=2)
+    ref = run_gpu(case, 20, blocks=inputs.uniform_blocks(dims, (2, 2, 1)), precision=precision)
+    for blocks in (None, inputs.uniform_blocks(dims, (1, 2, 1)), inputs.uniform_blocks(dims, (2, 1, 1))):
+        lat = run_gpu(case, 20, blocks=blocks, precision=precision)
+        assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+        lat.close()
+
+
+def test_self_wrapping_periodic_box_matches_oracle():
+    """Fully periodic box as one Block (wraps on all three axes) against the
+    oracle, and against a two-Block tiling bit for bit."""
+    case = periodic_box(dims=(70, 9, 7))
+    lat = run_gpu(case, 30)
+    o = run_oracle(case, 30)
+    check_vs_oracle(lat, o, TOL["f64"])
+    two = run_gpu(case, 30, blocks=inputs.uniform_blocks((70, 9, 7), (2, 1, 1)))
+    assert np.array_equal(lat.get_state(as_fp64=False), two.get_state(as_fp64=False))
+
+
 SCHEDULES = [
     dict(fused_exchange=0),
     dict(fused_exchange=2),

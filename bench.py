@@ -111,13 +111,26 @@ def copy_probe(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(p, solid, seconds=15.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, solid, seconds=12.0, single_steps=3):
     """The CPU FP64 oracle on the host cores, on a bounded sample of the same
-    workload (the full domain for as many steps as fit in ~seconds)."""
+    workload: the full domain for as many steps as fit in ~seconds on all
+    OpenMP threads, then `single_steps` steps on one thread."""
     import oracle
     o = oracle.OracleLBM(p["dims"], walls=p["walls"], wall_u=p["wall_u"], tau=p["tau"], force=p["force"])
     if solid is not None:
         o.set_geometry(solid)
+    cores = oracle.max_threads()
     o.step(1)  # touch memory
     t0 = time.perf_counter()
     n = 0
@@ -125,13 +138,18 @@ def cpu_baseline(p, solid, seconds=15.0):
         o.step(1)
         n += 1
     dt = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.step(single_steps)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
     cells = o.ncell if solid is None else int((solid == 0).sum())
     o.close()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=round(cells * n / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
-                sample="%s full domain %s, %d steps after 1 warm-up, FP64, %d OpenMP threads"
-                       % ("x".join(map(str, p["dims"])), "porous" if solid is not None else "",
-                          n, cores))
+                sample="%s full domain%s: %d steps after 1 warm-up on %d OpenMP threads, then %d steps on 1 "
+                       "thread; FP64" % ("x".join(map(str, p["dims"])), " (porous)" if solid is not None else "",
+                                         n, cores, single_steps),
+                single_thread_value=round(cells * single_steps / dt1 / 1e6, 3), cpu_model=cpu_model())
 
 
 def main():

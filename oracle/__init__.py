@@ -21,6 +21,15 @@ _lib = None
 FACES = ("-x", "+x", "-y", "+y", "-z", "+z")
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's step (timing on one and on all cores)."""
+    _load().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(_load().orc_max_threads())
+
+
 def build(force=False):
     """Compile the C oracle with gcc (OpenMP over z planes)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -52,6 +61,8 @@ def _load():
         lib.orc_set_state.argtypes = [P, dp, dp, dp]
         lib.orc_steps.argtypes = [P]
         lib.orc_steps.restype = ctypes.c_long
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_max_threads.restype = ctypes.c_int
         lib.orc_velocity.argtypes = [ctypes.c_int, ip]
         lib.orc_weight.argtypes = [ctypes.c_int]
         lib.orc_weight.restype = ctypes.c_double

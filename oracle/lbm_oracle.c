@@ -47,6 +47,7 @@
  * OpenMP only splits the z loop of the step; every cell is computed by the
  * same serial code, so the result does not depend on the thread count.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -321,3 +322,7 @@ long orc_steps(const orc_lbm *L) { return L->steps; }
 int orc_q(void) { return Q; }
 void orc_velocity(int i, int *e) { e[0] = E[i][0]; e[1] = E[i][1]; e[2] = E[i][2]; }
 double orc_weight(int i) { return weight_of(i); }
+
+/* Threads of the OpenMP z loop (timing of the baseline on 1 and all cores). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

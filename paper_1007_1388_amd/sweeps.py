@@ -10,8 +10,9 @@ blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
         the 512x256x256 porous channel as its uneven Blocks; per-launch times
         of the sweep and of the separate ghost exchange (HIP events) for the
         three exchange schedules (0 copy kernel, 2 x faces written by the
-        sweep, 1 fully fused): the cost of Blocks and of their on-GPU copies,
-        Sec. 5.2.
+        sweep, 1 fully fused), for the porous channel in its uneven Blocks and
+        for 64 uneven Blocks (4x4x4, edges from {32, 48, 64}): the cost of
+        Blocks and of their on-GPU copies, Sec. 5.2.
 
 Prints one JSON line per case.
 """
@@ -80,6 +81,15 @@ def block_sweep(steps):
                     force=p["force"], fused=fused)
         print(json.dumps(dict(study="blocks", domain="porous 512x256x256", split="uneven {32,48,64}",
                               precision="f32", fused=fused, **r)), flush=True)
+    # the literal 64 uneven Blocks: a 4x4x4 grid with edges from {32, 48, 64},
+    # the domain being whatever the edges sum to
+    dims, blocks = inputs.uneven_blocks_grid((4, 4, 4), p["block_edges"], seed=0)
+    solid = inputs.porous_spheres(dims, p["solid_fraction"], p["radius"], seed=0)
+    for fused in (0, 2, 1):
+        r = measure(dims, "f32", steps, blocks=blocks, solid=solid, walls=p["walls"], tau=p["tau"],
+                    force=p["force"], fused=fused)
+        print(json.dumps(dict(study="blocks", domain="porous %s" % "x".join(map(str, dims)),
+                              split="4x4x4 uneven {32,48,64}", precision="f32", fused=fused, **r)), flush=True)
 
 
 def main():

@@ -113,3 +113,38 @@ def test_porous512_full_partition_invariance_and_windows():
         scale = max(np.abs(u_o).max(), 1e-12)
         assert np.abs(ua[:, z, y, x] - u_o).max() <= 1e-5 * scale + 1e-12, (x, y, z)
         assert abs(ra[z, y, x] - r_o) <= 1e-6
+
+
+@pytest.mark.slow
+def test_porous512_full_domain_against_oracle_100_steps():
+    """The whole 512x256x256 porous channel in its 250 uneven Blocks (default
+    schedule: x faces written by the sweep, the rest by the copy kernel)
+    against the FP64 oracle of the whole domain after 100 steps: velocity and
+    every population, FP64 storage to 1e-12, FP32 storage to 1e-5.  (The
+    density itself is compared through the populations: rho = rho0 + drho in
+    FP64 resolves drho only to ~1e-16, which at this flow scale, |u| ~ 1e-4,
+    is already 1e-12 relative.)"""
+    p = inputs.preset("porous512")
+    solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
+    blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
+    steps = 100
+    o = oracle.OracleLBM(p["dims"], walls=p["walls"], tau=p["tau"], force=p["force"])
+    o.set_geometry(solid)
+    o.step(steps)
+    _, u_o = o.macroscopic()
+    f_o = o.get_state()
+    o.close()
+    fluid = solid == 0
+    scale = max(np.abs(f_o).max(), np.abs(np.asarray(p["force"])).max())
+    for precision, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        lat = gpu_lattice(p, blocks=blocks, precision=precision)
+        lat.set_geometry(solid)
+        lat.step(steps)
+        _, u_g = lat.macroscopic()
+        du = u_g[:, fluid] - u_o[:, fluid]
+        u_inf = np.abs(du).max() / np.abs(u_o[:, fluid]).max()
+        f_g = lat.get_state()
+        lat.close()
+        f_err = np.abs(f_g - f_o).max() / scale
+        del f_g
+        assert u_inf <= tol and f_err <= tol, (precision, u_inf, f_err)

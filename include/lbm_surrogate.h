@@ -54,7 +54,10 @@ lbm_status lbm_conv3d_bwd_data(const lbm_tensor5* dy, const uint16_t* w_t, const
                                void* stream);
 
 /* Gradient with respect to the weights and bias, ADDED (FP32 atomics) into
- * dw[co][kpad] and dbias[Cout] (dbias may be NULL).  Clear them first. */
+ * dw[co][kpad] and dbias[Cout] (dbias may be NULL).  Clear them first.  The
+ * summation order of the atomics varies from run to run, so results agree
+ * to FP32 rounding, not bit for bit.  LBM_EINVAL if dbias is given with
+ * Cout > 2048. */
 lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, float* dw, float* dbias,
                                  int32_t ksize, int32_t stride, void* stream);
 

@@ -15,6 +15,9 @@ SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "conv3d.hip"]
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-munsafe-fp-atomics", "-Wno-unused-result"]
+# per-source extras: the convolution kernels keep MFMA accumulators in
+# VGPRs, which spares the AGPR copies the K loop otherwise carries
+EXTRA = {"conv3d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc():
@@ -30,7 +33,7 @@ def build(verbose=False, jobs=3):
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     for s in srcs:
         obj = os.path.join(CSRC, "_" + s.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPFLAGS, "-c", os.path.join(CSRC, s), "-o", obj]
+        cmd = [hipcc(), *HIPFLAGS, *EXTRA.get(s, []), "-c", os.path.join(CSRC, s), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd)))

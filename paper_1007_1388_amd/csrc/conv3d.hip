@@ -151,6 +151,254 @@ __global__ void __launch_bounds__(256) k_conv_gemm(const uint16_t* __restrict__ 
   }
 }
 
+// ------------------------------------------- fwd / bwd-data, tap-major
+// The same products with the K loop ordered tap by tap (C gathered channels
+// per tap, C a multiple of 32), for the shapes where that holds:
+//  * each wave's A operand goes straight from memory into the MFMA registers
+//    (lane = row l%16, K group l/16: one 16-byte load of 8 channels of the
+//    tap's source voxel), through a raw buffer resource whose range check
+//    returns zeros for taps outside the volume;
+//  * every row's tap validity is a bit mask computed once, and the tap
+//    offset is uniform per K step, so a K step costs each lane one add, one
+//    select and one load per A fragment;
+//  * the weight tile (shared by the four waves) is double-buffered in LDS,
+//    one barrier per K step, and the next step's loads are in flight while
+//    the current step's MFMAs run;
+//  * the stride-2 input gradient runs per output parity class (grid.z): an
+//    input voxel i receives only from taps k with k = i + 1 mod 2 on every
+//    axis, so each class runs its 1, 2, 4 or 8 taps instead of 27.
+// A wave owns FM 16-row fragments and all 16*FN columns of the tile.
+struct DArgs {
+  const uint16_t* src;
+  Geo gs;
+  unsigned src_bytes;  // range of the gathered view, for the buffer resource
+  const uint16_t* wk;
+  int kstride;         // weight row length
+  unsigned wk_bytes;
+  const float* bias;
+  uint16_t* out;
+  Geo go;
+  const uint16_t* act;
+  int act_ldc;
+  int ksize, stride, relu, accumulate, C;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+
+template <int MODE, bool CLS, int FM, int FN>
+__global__ void __launch_bounds__(256) k_conv_tap(DArgs a) {
+  constexpr int BN = 16 * FN, WM = 16 * FM, BMW = 4 * WM;
+  constexpr int LDB = 40;  // padded weight-tile row (bf16)
+  constexpr unsigned OOB = 0x80000000u;
+  // weight chunks per thread (BN rows x 4 chunks of 8); rows past BN are
+  // spare, so that every thread stores and the loop has no branch
+  constexpr int NB = (BN * 4 + 255) / 256;
+  constexpr int BROWS = NB * 64;
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BROWS * LDB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Geo gs = a.gs, go = a.go;
+  const int pad = a.ksize == 3 ? 1 : 0;
+  // parity class and its row grid (CLS), else the whole output grid
+  int pcl[3] = {0, 0, 0};
+  int cd = go.d, ch = go.h, cw = go.w;
+  if (CLS) {
+    pcl[0] = blockIdx.z & 1;
+    pcl[1] = (blockIdx.z >> 1) & 1;
+    pcl[2] = (blockIdx.z >> 2) & 1;
+    cd = (go.d - pcl[0] + 1) >> 1;
+    ch = (go.h - pcl[1] + 1) >> 1;
+    cw = (go.w - pcl[2] + 1) >> 1;
+  }
+  // per-axis tap lists: entry j has kernel index kk(j) and source shift dl(j)
+  //   MODE 0:        kk = j, source = o*stride - pad + j
+  //   MODE 1, s = 1: kk = j, source = i + pad - j
+  //   MODE 1, s = 2: kk = p ? 2j : 1, source = (i + 1)/2 - j  (p = i mod 2)
+  int na[3];
+  for (int x = 0; x < 3; ++x) na[x] = CLS ? (pcl[x] ? 2 : 1) : a.ksize;
+  const int Mrows = go.n * cd * ch * cw;
+  const int m0 = blockIdx.x * BMW + wave * WM;
+
+  int basef[FM], voxf[FM];
+  unsigned mskf[FM];
+#pragma unroll
+  for (int f = 0; f < FM; ++f) {
+    const int m = m0 + f * 16 + (lane & 15);
+    const bool ok = m < Mrows;
+    int r = ok ? m : 0;
+    int c3[3];
+    c3[2] = r % cw; r /= cw;
+    c3[1] = r % ch; r /= ch;
+    c3[0] = r % cd;
+    const int n = r / cd;
+    if (CLS)
+      for (int x = 0; x < 3; ++x) c3[x] = 2 * c3[x] + pcl[x];
+    voxf[f] = ok ? ((n * go.d + c3[0]) * go.h + c3[1]) * go.w + c3[2] : -1;
+    const int ext[3] = {gs.d, gs.h, gs.w};
+    int b3[3];
+    unsigned v3[3];
+    for (int x = 0; x < 3; ++x) {
+      b3[x] = MODE == 0 ? c3[x] * a.stride - pad : (CLS ? (c3[x] + 1) >> 1 : c3[x] + pad);
+      unsigned v = 0;
+      for (int j = 0; j < na[x]; ++j) {
+        const int sx = MODE == 0 ? b3[x] + j : b3[x] - j;
+        if (sx >= 0 && sx < ext[x]) v |= 1u << j;
+      }
+      v3[x] = v;
+    }
+    unsigned mm = 0;
+    for (int jd = 0; jd < na[0]; ++jd)
+      for (int jh = 0; jh < na[1]; ++jh)
+        for (int jw = 0; jw < na[2]; ++jw)
+          if ((v3[0] >> jd) & (v3[1] >> jh) & (v3[2] >> jw) & 1u) mm |= 1u << ((jd * na[1] + jh) * na[2] + jw);
+    mskf[f] = ok ? mm : 0u;
+    basef[f] = (((n * gs.d + b3[0]) * gs.h + b3[1]) * gs.w + b3[2]) * gs.ldc + (lane >> 4) * 8;
+  }
+
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(a.src, a.src_bytes);
+  const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wk, a.wk_bytes);
+  const int n0 = blockIdx.y * BN;
+  const int ncols = go.c;
+  const int cpt = a.C >> 5;  // K steps per tap
+  const int nsub = na[0] * na[1] * na[2] * cpt;
+
+  // uniform K-step state: tap position (jd, jh, jw) and channel offset c0
+  struct St {
+    int jd, jh, jw, c0;
+  };
+  auto tap_of = [&](const St& q, int& off, int& bit, int& t) {
+    int dd, dh, dw, kd, kh, kw;
+    if (CLS) {
+      dd = -q.jd; dh = -q.jh; dw = -q.jw;
+      kd = pcl[0] ? 2 * q.jd : 1; kh = pcl[1] ? 2 * q.jh : 1; kw = pcl[2] ? 2 * q.jw : 1;
+    } else {
+      dd = MODE == 0 ? q.jd : -q.jd; dh = MODE == 0 ? q.jh : -q.jh; dw = MODE == 0 ? q.jw : -q.jw;
+      kd = q.jd; kh = q.jh; kw = q.jw;
+    }
+    off = ((dd * gs.h + dh) * gs.w + dw) * gs.ldc + q.c0;
+    bit = (q.jd * na[1] + q.jh) * na[2] + q.jw;
+    t = (kd * a.ksize + kh) * a.ksize + kw;
+  };
+  // branch-free, so that the K loop stays one loop
+  auto advance = [&](St& q) {
+    q.c0 += 32;
+    const int cw_ = q.c0 == a.C;
+    q.c0 = cw_ ? 0 : q.c0;
+    q.jw += cw_;
+    const int ww = q.jw == na[2];
+    q.jw = ww ? 0 : q.jw;
+    q.jh += ww;
+    const int hw = q.jh == na[1];
+    q.jh = hw ? 0 : q.jh;
+    q.jd += hw;
+  };
+  // An offset with the high bit set lies past the buffer's range, which
+  // loads zeros without touching memory (proper offsets stay below 2^31).
+  // `dead` is OOB for the step after the last, so every step issues the same
+  // loads, with no branch, and the waits stay exact.
+  auto load_a = [&](int off, int bit, unsigned dead, u32x4* dst) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      const unsigned vo = (unsigned)(basef[f] + off) * 2u | ((~(mskf[f] >> bit) & 1u) << 31) | dead;
+      dst[f] = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, 0, 0);
+    }
+  };
+  // per-thread weight offsets; the high bit sends a spare or missing row
+  // out of range (offsets proper stay below 2^31)
+  unsigned boff[NB], bpen[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int id = tid + i * 256;
+    const int r = id >> 2, chk = id & 3;
+    const bool ok = id < BN * 4 && n0 + r < ncols;
+    boff[i] = (unsigned)((ok ? n0 + r : 0) * a.kstride + chk * 8) * 2u;
+    bpen[i] = ok ? 0u : OOB;
+  }
+  auto load_b = [&](int t, int c0, unsigned dead, u32x4* dst) {
+    const unsigned kb = (unsigned)(t * a.C + c0) * 2u;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      dst[i] = __builtin_amdgcn_raw_buffer_load_b128(rw, (boff[i] + kb) | bpen[i] | dead, 0, 0);
+  };
+  auto store_b = [&](int buf, const u32x4* v) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int id = tid + i * 256;
+      *(u32x4*)(&Bs[buf][(id >> 2) * LDB + (id & 3) * 8]) = v[i];
+    }
+  };
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  St st{0, 0, 0, 0};
+  u32x4 acur[FM], anxt[FM], breg[NB];
+  {
+    int off, bit, t;
+    tap_of(st, off, bit, t);
+    load_b(t, 0, 0u, breg);
+    load_a(off, bit, 0u, acur);
+  }
+  store_b(0, breg);
+  __syncthreads();
+  // K step s: issue the loads of step s + 1 (weights first, so that staging
+  // them waits for no A load), multiply step s (operands in acur, weights in
+  // LDS buffer s & 1), then stage the next weights
+  // two steps per iteration, the A registers alternating between acur and
+  // anxt, so that a load is first waited for one step after its issue
+#define LBM_CONV_KSTEP(S, CUR, NXT)                                                                          \
+  {                                                                                                        \
+    advance(st);                                                                                           \
+    const unsigned dead = (unsigned)(nsub - 2 - (S)) & OOB; /* S + 1 == nsub */                            \
+    int off, bit, t;                                                                                       \
+    tap_of(st, off, bit, t);                                                                               \
+    load_b(t, st.c0, dead, breg);                                                                          \
+    load_a(off, bit, dead, NXT);                                                                           \
+    __builtin_amdgcn_sched_barrier(0); /* the loads stay ahead of the MFMAs */                             \
+    const uint16_t* B = Bs[(S) & 1];                                                                       \
+    _Pragma("unroll") for (int j = 0; j < FN; ++j) {                                                       \
+      const bf16x8 b = *(const bf16x8*)(B + (j * 16 + (lane & 15)) * LDB + (lane >> 4) * 8);               \
+      _Pragma("unroll") for (int f = 0; f < FM; ++f) acc[f][j] =                                           \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, CUR[f]), b, acc[f][j], 0, 0, 0); \
+    }                                                                                                      \
+    store_b(((S) + 1) & 1, breg);                                                                          \
+    __syncthreads();                                                                                       \
+  }
+  int s = 0;
+  for (; s + 1 < nsub; s += 2) {
+    LBM_CONV_KSTEP(s, acur, anxt)
+    LBM_CONV_KSTEP(s + 1, anxt, acur)
+  }
+  if (s < nsub) LBM_CONV_KSTEP(s, acur, anxt)
+#undef LBM_CONV_KSTEP
+  // ---- epilogue: lane holds D[(lane/16)*4 + r][lane%16] of each 16x16 tile;
+  // the voxel of D row q is held by lane q (A layout row q)
+#pragma unroll
+  for (int f = 0; f < FM; ++f) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int vo = __shfl(voxf[f], (lane >> 4) * 4 + r);
+      if (vo < 0) continue;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + j * 16 + (lane & 15);
+        if (n >= ncols) continue;
+        float v = acc[f][j][r];
+        if (a.bias) v += a.bias[n];
+        if (a.relu) v = v > 0.f ? v : 0.f;
+        const long long o = (long long)vo * go.ldc + n;
+        if (a.act && !(bf2f(a.act[(long long)vo * a.act_ldc + n]) > 0.f)) v = 0.f;
+        if (a.accumulate) v += bf2f(a.out[o]);
+        a.out[o] = f2bf(v);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- bwd-weight
 // C[co][k] += sum over voxels v of dy[v][co] * patch(x)[v][k].  Rows = co
 // (BM = 128 covers every Cout here in one or two tiles), columns = k
@@ -232,16 +480,240 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const uint16_t* __restrict__
     }
 }
 
-// dbias[co] += sum_v dy[v][co]
+// ------------------------------------------------- bwd-weight, 3x3x3 halos
+// dw[co][tap*Cin + ci] += sum_v dy[v][co] * x[src(v, tap)][ci] for 3x3x3
+// kernels with Cin a multiple of 32.  A workgroup owns one kernel plane kd,
+// 32 input channels and BM output channels, i.e. a BM x (9 taps x 32) block
+// of dw, and walks a range of 32-voxel steps of dy (R rows of W' voxels,
+// W' = min(W, 32)).  Per step it stages, in their channels-last order,
+//   * the dy tile  [32 voxels][BM channels] and
+//   * the x halo   [(R-1)s+3 rows][(W'-1)s+3 columns][32 channels] of plane
+//     z = d*s + kd - 1, which holds the sources of all nine (kh, kw) taps;
+// both MFMA operands (voxels as K) are then read from LDS by the transposing
+// read ds_read_b64_tr_b16 (a 16-lane group gives the addresses of four rows
+// of four 16-bit values; lane l receives column l%16 of that 4 x 16 block),
+// so the halo is staged once for nine taps and no lane transposes by hand.
+// Tiles are double-buffered; out-of-range sources and voxels load zeros
+// through the buffer range check.  Each wave keeps 9 x BM/32 accumulator
+// tiles and adds them to dw once at the end (FP32 atomics).
+struct WArgs {
+  const uint16_t* x;
+  Geo gx;
+  unsigned x_bytes;
+  const uint16_t* dy;
+  Geo gy;
+  unsigned dy_bytes;
+  float* dw;
+  int kpad;
+  int wp, r, nhb, nwb;  // step shape: R rows of W' voxels; steps per row block / plane
+  int steps, per_wg;    // total steps, steps per workgroup
+  int nco, nci;         // output / input channel tiles
+};
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+
+__device__ __forceinline__ bf16x8 tr_load8(const uint16_t* p, int off_lo, int off_hi) {
+  const __attribute__((address_space(3))) uint16_t* q = (const __attribute__((address_space(3))) uint16_t*)p;
+  const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(q + off_lo));
+  const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(q + off_hi));
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+template <int S, int BM>
+__global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
+  constexpr int PA = BM + 8;                 // dy tile row pitch (bf16)
+  constexpr int PC = 40;                     // halo cell pitch: 32 channels + 8
+  constexpr int CELLS = S == 1 ? 102 : 195;  // largest halo over the step shapes
+  constexpr int NAC = 32 * BM / 8;           // dy chunks of 8 channels
+  constexpr int NAP = (NAC + 255) / 256;
+  constexpr int NXP = (CELLS * 4 + 255) / 256;
+  constexpr int NSUB = BM / 32;              // 16-row output tiles per wave
+  constexpr unsigned OOB = 0x80000000u;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][32 * PA];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][CELLS * PC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Geo gx = a.gx, gy = a.gy;
+  int by = blockIdx.y;
+  const int co_t = by % a.nco;
+  by /= a.nco;
+  const int ci_t = by % a.nci;
+  const int kd = by / a.nci;
+  const int co0 = co_t * BM, ci0 = ci_t * 32;
+  const int wp = a.wp, rr = a.r;
+  const int hc = (wp - 1) * S + 3, ncell = ((rr - 1) * S + 3) * hc;
+
+  // staging roles (fixed per thread): dy chunk (voxel, channel group)
+  int a_v[NAP], a_q[NAP];
+  bool a_on[NAP];
+#pragma unroll
+  for (int i = 0; i < NAP; ++i) {
+    const int id = tid + i * 256;
+    a_v[i] = id / (BM / 8);
+    a_q[i] = id % (BM / 8);
+    a_on[i] = id < NAC && co0 + a_q[i] * 8 < gy.c;
+  }
+  int a_r[NAP], a_c[NAP];
+#pragma unroll
+  for (int i = 0; i < NAP; ++i) {
+    a_r[i] = (a_v[i] & 31) / wp;
+    a_c[i] = (a_v[i] & 31) % wp;
+  }
+  // halo chunk (cell, channel group)
+  int x_hr[NXP], x_hc[NXP], x_q[NXP];
+  bool x_on[NXP];
+#pragma unroll
+  for (int i = 0; i < NXP; ++i) {
+    const int id = tid + i * 256;
+    const int cell = id >> 2;
+    x_on[i] = cell < ncell;
+    x_hr[i] = cell / hc;
+    x_hc[i] = cell % hc;
+    x_q[i] = id & 3;
+  }
+  // operand read offsets: 16-lane group g covers voxels 8g..8g+7, half h
+  // the rows 8g+4h .. +3; lane L of the group addresses row L/4, columns
+  // (L%4)*4 .. +3 of its 16-column block
+  const int L = lane & 15, g = lane >> 4, jsub = wave & 1;
+  int aoff[NSUB][2], xoff[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int v = 8 * g + 4 * h + (L >> 2);
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) aoff[i][h] = v * PA + ((wave >> 1) * NSUB + i) * 16 + (L & 3) * 4;
+    xoff[h] = ((v / wp) * S * hc + (v % wp) * S) * PC + jsub * 16 + (L & 3) * 4;
+  }
+
+  const __amdgpu_buffer_rsrc_t rx = rsrc_of(a.x, a.x_bytes);
+  const __amdgpu_buffer_rsrc_t rd = rsrc_of(a.dy, a.dy_bytes);
+  const int s_begin = blockIdx.x * a.per_wg;
+  const int s_end = s_begin + a.per_wg < a.steps ? s_begin + a.per_wg : a.steps;
+  // uniform step coordinates, advanced without branches
+  int st = s_begin;
+  int wb = st % a.nwb, hb = (st / a.nwb) % a.nhb, pl = st / (a.nwb * a.nhb);
+  int nn = pl / gy.d, dd = pl % gy.d;
+  auto advance = [&]() {
+    ++wb;
+    const int c1 = wb == a.nwb;
+    wb = c1 ? 0 : wb;
+    hb += c1;
+    const int c2 = hb == a.nhb;
+    hb = c2 ? 0 : hb;
+    dd += c2;
+    const int c3 = dd == gy.d;
+    dd = c3 ? 0 : dd;
+    nn += c3;
+  };
+  u32x4 ar[NAP], xr[NXP];
+  auto load_step = [&](unsigned dead) {
+    const int h0 = hb * rr, w0 = wb * wp;
+#pragma unroll
+    for (int i = 0; i < NAP; ++i) {
+      const int hh = h0 + a_r[i], ww = w0 + a_c[i];
+      const bool ok = a_on[i] && hh < gy.h && ww < gy.w;
+      const unsigned vo =
+          (unsigned)((((nn * gy.d + dd) * gy.h + hh) * gy.w + ww) * gy.ldc + co0 + a_q[i] * 8) * 2u | (ok ? 0u : OOB);
+      ar[i] = __builtin_amdgcn_raw_buffer_load_b128(rd, vo | dead, 0, 0);
+    }
+    const int zs = dd * S + kd - 1, ys0 = h0 * S - 1, xs0 = w0 * S - 1;
+    const bool zok = zs >= 0 && zs < gx.d;
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) {
+      const int ys = ys0 + x_hr[i], xs = xs0 + x_hc[i];
+      const bool ok = x_on[i] && zok && ys >= 0 && ys < gx.h && xs >= 0 && xs < gx.w;
+      const unsigned vo =
+          (unsigned)((((nn * gx.d + zs) * gx.h + ys) * gx.w + xs) * gx.ldc + ci0 + x_q[i] * 8) * 2u | (ok ? 0u : OOB);
+      xr[i] = __builtin_amdgcn_raw_buffer_load_b128(rx, vo | dead, 0, 0);
+    }
+  };
+  auto store_step = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NAP; ++i)
+      if (tid + i * 256 < NAC) *(u32x4*)(&As[buf][(a_v[i] & 31) * PA + a_q[i] * 8]) = ar[i];
+#pragma unroll
+    for (int i = 0; i < NXP; ++i)
+      if (x_on[i]) *(u32x4*)(&Xs[buf][(x_hr[i] * hc + x_hc[i]) * PC + x_q[i] * 8]) = xr[i];
+  };
+
+  f32x4 acc[NSUB][9];
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (s_begin < s_end) {
+    load_step(0u);
+    store_step(0);
+    __syncthreads();
+  }
+  int buf = 0;
+  for (; st < s_end; ++st) {
+    advance();
+    load_step(st + 1 < s_end ? 0u : OOB);
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the MFMAs
+    const uint16_t* A = As[buf];
+    const uint16_t* X = Xs[buf];
+    bf16x8 af[NSUB];
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) af[i] = tr_load8(A, aoff[i][0], aoff[i][1]);
+#pragma unroll
+    for (int kh = 0; kh < 3; ++kh)
+#pragma unroll
+      for (int kw = 0; kw < 3; ++kw) {
+        const int to = (kh * hc + kw) * PC;
+        const bf16x8 bfr = tr_load8(X, xoff[0] + to, xoff[1] + to);
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i)
+          acc[i][kh * 3 + kw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][kh * 3 + kw], 0, 0, 0);
+      }
+    store_step(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane holds D[(lane/16)*4 + q][lane%16] of each tile: rows co, columns ci
+  const int cin = gx.c;
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = co0 + ((wave >> 1) * NSUB + i) * 16 + g * 4 + q;
+      if (co >= gy.c) continue;
+      const int ci = ci0 + jsub * 16 + L;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) atomicAdd(a.dw + (long long)co * a.kpad + (kd * 9 + t) * cin + ci, acc[i][t][q]);
+    }
+}
+
+// dbias[co] += sum_v dy[v][co]: a thread sums 8 channels (one 16-byte load
+// per voxel) over every (256 / groups)-th voxel of the workgroup's range; the
+// partial sums meet in LDS and each channel takes one atomic per workgroup.
 __global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* __restrict__ dy, Geo gy, float* __restrict__ db,
                                                    long long vox_per_wg) {
+  __shared__ float part[256 * 8];
   const long long V = (long long)gy.n * gy.d * gy.h * gy.w;
   const long long vbeg = (long long)blockIdx.x * vox_per_wg;
   const long long vend = vbeg + vox_per_wg < V ? vbeg + vox_per_wg : V;
-  for (int co = threadIdx.x; co < gy.c; co += blockDim.x) {
-    float s = 0.f;
-    for (long long v = vbeg; v < vend; ++v) s += bf2f(dy[v * gy.ldc + co]);
-    atomicAdd(db + co, s);
+  const int groups = gy.c / 8;         // at most 256 (host check)
+  const int vl = 256 / groups;         // voxel lanes
+  const int tid = threadIdx.x, cg = tid % groups, vi = tid / groups;
+  float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (vi < vl)
+    for (long long v = vbeg + vi; v < vend; v += vl) {
+      const u32x4 t = *(const u32x4*)(dy + v * gy.ldc + cg * 8);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s8[2 * j] += __uint_as_float(t[j] << 16);
+        s8[2 * j + 1] += __uint_as_float(t[j] & 0xffff0000u);
+      }
+    }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) part[tid * 8 + j] = s8[j];
+  __syncthreads();
+  for (int c = tid; c < gy.c; c += 256) {
+    const int g = c / 8, j = c % 8;
+    float t = 0.f;
+    for (int k = 0; k < vl; ++k) t += part[(k * groups + g) * 8 + j];
+    atomicAdd(db + c, t);
   }
 }
 
@@ -386,6 +858,33 @@ bool tensor_ok(const lbm_tensor5* t) {
 
 int outdim(int in, int stride) { return (in + stride - 1) / stride; }
 
+// bytes spanned by a channels-last view (last voxel's last channel included)
+long long view_bytes(const lbm_tensor5* t) {
+  return (((long long)t->n * t->d * t->h * t->w - 1) * t->ldc + t->c) * 2;
+}
+
+// the tap-major kernels index in 32 bits and address through buffer resources
+bool tap_fits(const lbm_tensor5* t) { return view_bytes(t) < (1ll << 31); }
+
+template <int MODE, bool CLS, int FM, int FN>
+void launch_tap(const DArgs& a, long long rows, int nz, hipStream_t s) {
+  constexpr int BMW = 64 * FM, BN = 16 * FN;
+  const dim3 g((unsigned)((rows + BMW - 1) / BMW), (unsigned)((a.go.c + BN - 1) / BN), (unsigned)nz);
+  hipLaunchKernelGGL((k_conv_tap<MODE, CLS, FM, FN>), g, dim3(256), 0, s, a);
+}
+
+// tile shape by output columns: 32 -> 64 rows x 32 per wave, 64 -> 32 x 64,
+// more -> 32 x 128 per column tile
+template <int MODE, bool CLS>
+void launch_tap_cols(const DArgs& a, long long rows, int nz, hipStream_t s) {
+  if (a.go.c <= 32)
+    launch_tap<MODE, CLS, 4, 2>(a, rows, nz, s);
+  else if (a.go.c <= 64)
+    launch_tap<MODE, CLS, 2, 4>(a, rows, nz, s);
+  else
+    launch_tap<MODE, CLS, 2, 8>(a, rows, nz, s);
+}
+
 int grid1(long long n) {
   long long g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -411,7 +910,12 @@ lbm_status lbm_conv3d_fwd(const lbm_tensor5* x, const uint16_t* w, const float* 
   hipStream_t s = (hipStream_t)stream;
   const Geo gs = geo_of(x), go = geo_of(y);
   const dim3 b(256);
-  if (y->c <= 16) {
+  if (x->c % 32 == 0 && tap_fits(x) && tap_fits(y)) {
+    const DArgs a{(const uint16_t*)x->ptr, gs, (unsigned)view_bytes(x), w, kpad,
+                  (unsigned)((long long)y->c * kpad * 2), bias, (uint16_t*)y->ptr, go, nullptr, 0, ksize, stride,
+                  relu, 0, x->c};
+    launch_tap_cols<0, false>(a, M, 1, s);
+  } else if (y->c <= 16) {
     dim3 g((unsigned)((M + BM - 1) / BM), (y->c + 15) / 16);
     hipLaunchKernelGGL((k_conv_gemm<0, 16>), g, b, 0, s, (const uint16_t*)x->ptr, gs, w, kpad, bias,
                        (uint16_t*)y->ptr, go, (const uint16_t*)nullptr, 0, ksize, stride, relu, 0, x->c);
@@ -447,7 +951,18 @@ lbm_status lbm_conv3d_bwd_data(const lbm_tensor5* dy, const uint16_t* w_t, const
   const uint16_t* ap = act ? (const uint16_t*)act->ptr : nullptr;
   const int aldc = act ? act->ldc : 0;
   const dim3 b(256);
-  if (dx->c <= 16) {
+  if (dy->c % 32 == 0 && tap_fits(dy) && tap_fits(dx)) {
+    const DArgs a{(const uint16_t*)dy->ptr, gs, (unsigned)view_bytes(dy), w_t, kpad,
+                  (unsigned)((long long)dx->c * kpad * 2), nullptr, (uint16_t*)dx->ptr, go, ap, aldc, ksize, stride,
+                  0, accumulate, dy->c};
+    if (stride == 2) {
+      // rows of the largest parity class; smaller classes mask their tail
+      const long long rows = (long long)dx->n * ((dx->d + 1) / 2) * ((dx->h + 1) / 2) * ((dx->w + 1) / 2);
+      launch_tap_cols<1, true>(a, rows, 8, s);
+    } else {
+      launch_tap_cols<1, false>(a, M, 1, s);
+    }
+  } else if (dx->c <= 16) {
     dim3 g((unsigned)((M + BM - 1) / BM), (dx->c + 15) / 16);
     hipLaunchKernelGGL((k_conv_gemm<1, 16>), g, b, 0, s, (const uint16_t*)dy->ptr, gs, w_t, kpad,
                        (const float*)nullptr, (uint16_t*)dx->ptr, go, ap, aldc, ksize, stride, 0, accumulate, dy->c);
@@ -470,11 +985,57 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     return LBM_EINVAL;
   if (dy->n != x->n || dy->d != outdim(x->d, stride) || dy->h != outdim(x->h, stride) || dy->w != outdim(x->w, stride))
     return LBM_EINVAL;
+  if (dbias && dy->c > 2048) return LBM_EINVAL;
   const int taps = ksize * ksize * ksize;
   const int kpad = lbm_conv_kpad(taps, x->c);
   const long long V = (long long)dy->n * dy->d * dy->h * dy->w;
   hipStream_t s = (hipStream_t)stream;
   const dim3 b(256);
+  const bool wfit = dy->w >= 32 ? true : (32 % dy->w) == 0;
+  if (ksize == 3 && x->c % 32 == 0 && wfit && tap_fits(x) && tap_fits(dy) && V < (1ll << 31)) {
+    WArgs a{};
+    a.x = (const uint16_t*)x->ptr;
+    a.gx = geo_of(x);
+    a.x_bytes = (unsigned)view_bytes(x);
+    a.dy = (const uint16_t*)dy->ptr;
+    a.gy = geo_of(dy);
+    a.dy_bytes = (unsigned)view_bytes(dy);
+    a.dw = dw;
+    a.kpad = kpad;
+    a.wp = dy->w >= 32 ? 32 : dy->w;
+    a.r = 32 / a.wp;
+    a.nhb = (dy->h + a.r - 1) / a.r;
+    a.nwb = (dy->w + a.wp - 1) / a.wp;
+    const long long steps = (long long)dy->n * dy->d * a.nhb * a.nwb;
+    const int bmw = dy->c <= 32 ? 32 : 64;
+    a.nco = (dy->c + bmw - 1) / bmw;
+    a.nci = x->c / 32;
+    const long long tiles = 3ll * a.nci * a.nco;
+    // about 2048 workgroups in all, at least 8 steps each
+    long long per = (steps * tiles + 2047) / 2048;
+    if (per < 8) per = 8;
+    const long long splits = (steps + per - 1) / per;
+    a.steps = (int)steps;
+    a.per_wg = (int)per;
+    const dim3 g((unsigned)splits, (unsigned)tiles);
+    if (stride == 1) {
+      if (bmw == 32)
+        hipLaunchKernelGGL((k_conv_wgrad_halo<1, 32>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_conv_wgrad_halo<1, 64>), g, b, 0, s, a);
+    } else {
+      if (bmw == 32)
+        hipLaunchKernelGGL((k_conv_wgrad_halo<2, 32>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_conv_wgrad_halo<2, 64>), g, b, 0, s, a);
+    }
+    if (dbias) {
+      const long long pb = 2048;
+      hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((V + pb - 1) / pb)), b, 0, s, (const uint16_t*)dy->ptr,
+                         geo_of(dy), dbias, pb);
+    }
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+  }
   const int gm = (dy->c + BM - 1) / BM, gn = (kpad + 63) / 64;
   // split the voxel range so that the grid holds about 2048 workgroups
   long long splits = 2048 / (gm * gn);
@@ -486,7 +1047,7 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
   hipLaunchKernelGGL(k_conv_wgrad, g, b, 0, s, (const uint16_t*)x->ptr, geo_of(x), (const uint16_t*)dy->ptr,
                      geo_of(dy), dw, kpad, x->c, ksize, stride, per);
   if (dbias) {
-    long long pb = 4096;
+    const long long pb = 2048;
     hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((V + pb - 1) / pb)), b, 0, s, (const uint16_t*)dy->ptr,
                        geo_of(dy), dbias, pb);
   }

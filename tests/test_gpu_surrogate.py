@@ -31,6 +31,23 @@ CASES = [
     dict(n=1, d=5, h=7, w=9, ci=64, co=80, k=3, s=1),
     dict(n=2, d=4, h=4, w=6, ci=32, co=8, k=1, s=1),
     dict(n=1, d=9, h=3, w=5, ci=24, co=16, k=3, s=2),
+    # gathered channels a multiple of 32: the tap-major kernels, every tile
+    # shape (32, 64, 128 columns and a partial second column tile), the
+    # stride-2 input gradient by parity classes on odd and even extents
+    dict(n=2, d=7, h=6, w=9, ci=32, co=64, k=3, s=2),
+    dict(n=1, d=6, h=5, w=11, ci=64, co=32, k=3, s=1),
+    dict(n=1, d=4, h=6, w=8, ci=128, co=160, k=3, s=1),
+    dict(n=1, d=5, h=3, w=7, ci=32, co=32, k=1, s=1),
+    dict(n=1, d=9, h=4, w=5, ci=96, co=128, k=3, s=2),
+    # weight gradient by halos (3x3x3, Cin a multiple of 32, dy width a
+    # divisor of 32 or at least 32): rows of 16, 8 and 2 voxels per step,
+    # partial row blocks, a partial second 32-voxel block, both strides, a
+    # partial output-channel tile
+    dict(n=1, d=5, h=6, w=16, ci=32, co=32, k=3, s=1),
+    dict(n=2, d=3, h=5, w=40, ci=32, co=64, k=3, s=1),
+    dict(n=1, d=6, h=7, w=16, ci=64, co=48, k=3, s=2),
+    dict(n=1, d=4, h=5, w=2, ci=32, co=32, k=3, s=1),
+    dict(n=1, d=3, h=3, w=70, ci=32, co=32, k=3, s=2),
 ]
 
 

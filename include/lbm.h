@@ -60,16 +60,31 @@ typedef enum {
  * round-to-nearest-even, and always compute in FP32. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_precision;
 
-typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face;
+/* Face kinds.  PERIODIC faces come in opposite pairs.  VELOCITY and
+ * PRESSURE are open faces (x faces only): the boundary node one cell beyond
+ * the face, next to the domain cell x_f, holds the post-collision
+ * populations of the non-equilibrium extrapolation rule (Guo, Zheng and Shi,
+ * 2002; on-GPU boundary conditions are the paper's stated future work,
+ * Sec. 5.1 and the conclusion):
+ *     f~_i(x_b) = feq~_i(drho_b, u_b) + f~*_i(x_f) - feq~_i(drho_f, u_f),
+ * drho_f and u_f being the moments of x_f's last collision.  VELOCITY
+ * prescribes u_b = wall_u[face] and takes drho_b = drho_f; PRESSURE
+ * prescribes rho_b = face_rho[face] and takes u_b = u_f.  A link whose
+ * source lies beyond a WALL face as well bounces back (walls take
+ * precedence).  Open faces need one Block across y and across z, and no
+ * solid cell on the face. */
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_VELOCITY = 2, LBM_PRESSURE = 3 } lbm_face;
 
 /* Half-open global cell box [lo, hi) of one Block (the Block AABB, Sec. 4.2). */
 typedef struct { int32_t lo[3], hi[3]; } lbm_aabb;
 
 typedef struct {
   int32_t dims[3];        /* nx, ny, nz of the single Patch, each >= 1 */
-  int32_t face[6];        /* lbm_face of -x,+x,-y,+y,-z,+z; opposite faces must match */
-  double wall_u[6][3];    /* wall velocity per face; its normal component must be 0,
-                             and it must be 0 on PERIODIC faces */
+  int32_t face[6];        /* lbm_face of -x,+x,-y,+y,-z,+z: both faces of an axis
+                             PERIODIC, or each WALL, VELOCITY or PRESSURE (the
+                             last two on x faces only) */
+  double wall_u[6][3];    /* WALL faces: wall velocity, tangential; VELOCITY faces: the
+                             prescribed velocity (any direction); 0 on other faces */
   double tau;             /* BGK relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
   double rho0;            /* reference density, > 0 (1 for all presets) */
   double force[3];        /* body force g per unit mass, lattice units */
@@ -85,6 +100,8 @@ typedef struct {
                              128 bytes and then row_pad more 128-byte lines are added;
                              0 = automatic, -1 = none (layout only; results do not depend
                              on it) */
+  double face_rho[6];     /* PRESSURE faces: the prescribed density (> 0); ignored
+                             on other faces */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -66,6 +66,8 @@ def _load():
         lib.orc_velocity.argtypes = [ctypes.c_int, ip]
         lib.orc_weight.argtypes = [ctypes.c_int]
         lib.orc_weight.restype = ctypes.c_double
+        lib.orc_set_xface.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double]
+        lib.orc_set_xface.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -78,11 +80,14 @@ class OracleLBM:
     """One global FP64 lattice; arrays are numpy, cell index (z, y, x).
 
     dims = (nx, ny, nz); walls = per-axis flag (True: half-way bounce-back
-    walls on both faces, False: periodic); wall_u = {face: (ux, uy, uz)}.
+    walls on both faces, False: periodic); wall_u = {face: (ux, uy, uz)};
+    open_x = {"-x" or "+x": ("velocity", (ux, uy, uz)) | ("pressure", rho) |
+    "wall"}: open x faces by non-equilibrium extrapolation (a face not named
+    keeps what `walls` says; x must not be periodic then).
     """
 
     def __init__(self, dims, walls=(False, False, False), wall_u=None, tau=0.6,
-                 rho0=1.0, force=(0.0, 0.0, 0.0)):
+                 rho0=1.0, force=(0.0, 0.0, 0.0), open_x=None):
         lib = _load()
         self.dims = tuple(int(d) for d in dims)
         self.rho0 = float(rho0)
@@ -98,6 +103,18 @@ class OracleLBM:
         if not self._h:
             raise ValueError("oracle: invalid parameters")
         self._lib = lib
+        for face, spec in (open_x or {}).items():
+            side = {"-x": 0, "+x": 1}[face]
+            if spec == "wall":
+                kind, u, rho = 1, np.zeros(3), 0.0
+            elif spec[0] == "velocity":
+                kind, u, rho = 2, np.asarray(spec[1], dtype=np.float64), 0.0
+            elif spec[0] == "pressure":
+                kind, u, rho = 3, np.zeros(3), float(spec[1])
+            else:
+                raise ValueError("oracle: bad open face %r" % (spec,))
+            if lib.orc_set_xface(self._h, side, kind, _dptr(u), rho) != 0:
+                raise ValueError("oracle: bad open face")
         nx, ny, nz = self.dims
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz

@@ -30,6 +30,20 @@
  *             g'_i(x) = f_i - (1/tau)(f_i - feq~_i) + (1 - 1/(2 tau)) F_i.
  *   Solid cells are never updated and always hold 0; they report rho0 and 0.
  *
+ * Open x faces (an extension: the paper names boundary conditions computed
+ * on the GPU as future work, Sec. 5.1 and the conclusion): a VELOCITY or
+ * PRESSURE face replaces the wall or the periodic image by a boundary node
+ * one cell outside, whose post-collision populations follow the
+ * non-equilibrium extrapolation rule of Guo, Zheng and Shi (2002):
+ *     g_i(x_b) = feq~_i(drho_b, u_b) + [ g_i(x_f) - feq~_i(drho_f, u_f) ],
+ * x_f the domain cell next to x_b (same y, z), drho_f and u_f the moments of
+ * x_f rebuilt from its post-collision populations (drho = sum g,
+ * u = sum e g / rho0 - g/2: the collision keeps drho and adds rho0 g to the
+ * momentum).  A velocity face prescribes u_b and takes drho_b = drho_f; a
+ * pressure face prescribes drho_b = rho_b - rho0 and takes u_b = u_f.  A link
+ * whose source lies beyond a wall face as well bounces back (walls take
+ * precedence).  Solid cells must not lie on an open face.
+ *
  * Readings of points the paper leaves open (each stated where it is used):
  *   - 19 directions i = 0..18 (the equation's index range printed as 0..19
  *     is taken as a typo; the text speaks of 19 PDFs);
@@ -63,9 +77,14 @@ static const int E[Q][3] = {
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_VELOCITY = 2, ORC_PRESSURE = 3 };
+
 typedef struct {
     int n[3];          /* nx, ny, nz */
     int wall[3];       /* per axis: 0 periodic, 1 half-way bounce-back walls */
+    int kind[6];       /* per face -x,+x,-y,+y,-z,+z: ORC_* */
+    double ob_u[2][3]; /* prescribed velocity of an open -x / +x face */
+    double ob_rho[2];  /* prescribed density of an open -x / +x face */
     double uw[6][3];   /* wall velocity of faces -x,+x,-y,+y,-z,+z */
     double tau, rho0;
     double g[3];       /* body force per unit mass, lattice units */
@@ -125,6 +144,7 @@ orc_lbm *orc_create(const int *dims, const int *wall_axis, const double *wall_u,
     for (int a = 0; a < 3; ++a) {
         L->n[a] = dims[a];
         L->wall[a] = wall_axis[a] ? 1 : 0;
+        L->kind[2 * a] = L->kind[2 * a + 1] = L->wall[a] ? ORC_WALL : ORC_PERIODIC;
         L->g[a] = g ? g[a] : 0.0;
     }
     for (int f = 0; f < 6; ++f)
@@ -148,6 +168,19 @@ orc_lbm *orc_create(const int *dims, const int *wall_axis, const double *wall_u,
     }
     reset_rest(L);
     return L;
+}
+
+/* Make x face `side` (0: -x, 1: +x) open: kind ORC_VELOCITY with velocity
+ * u[3], or ORC_PRESSURE with density rho; ORC_WALL or ORC_PERIODIC restore
+ * those (a periodic x needs both faces periodic).  Returns 0, or -1 on a bad
+ * argument. */
+int orc_set_xface(orc_lbm *L, int side, int kind, const double *u, double rho) {
+    if (side < 0 || side > 1 || kind < ORC_PERIODIC || kind > ORC_PRESSURE) return -1;
+    L->kind[side] = kind;
+    for (int a = 0; a < 3; ++a) L->ob_u[side][a] = (kind == ORC_VELOCITY && u) ? u[a] : 0.0;
+    L->ob_rho[side] = kind == ORC_PRESSURE ? rho : L->rho0;
+    L->wall[0] = L->kind[0] != ORC_PERIODIC || L->kind[1] != ORC_PERIODIC;
+    return 0;
 }
 
 /* Solid mask [z][y][x] (1 = solid), NULL = all fluid; resets to rest. */
@@ -181,6 +214,29 @@ void orc_set_equilibrium(orc_lbm *L, const double *rho, const double *u) {
     L->steps = 0;
 }
 
+/* Post-collision population i of the boundary node one cell beyond open x
+ * face `side`, next to the domain cell xf (non-equilibrium extrapolation,
+ * see the file header). */
+static double open_node(const orc_lbm *L, int side, int i, size_t xf) {
+    const size_t N = L->ncell;
+    double drho_f = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < Q; ++k) {
+        const double v = L->f[(size_t)k * N + xf];
+        drho_f += v;
+        for (int a = 0; a < 3; ++a) j[a] += E[k][a] * v;
+    }
+    double u_f[3], u_b[3], drho_b;
+    for (int a = 0; a < 3; ++a) u_f[a] = j[a] / L->rho0 - 0.5 * L->g[a];
+    if (L->kind[side] == ORC_VELOCITY) {
+        for (int a = 0; a < 3; ++a) u_b[a] = L->ob_u[side][a];
+        drho_b = drho_f;
+    } else {
+        for (int a = 0; a < 3; ++a) u_b[a] = u_f[a];
+        drho_b = L->ob_rho[side] - L->rho0;
+    }
+    return feq_shifted(L, i, drho_b, u_b) + L->f[(size_t)i * N + xf] - feq_shifted(L, i, drho_f, u_f);
+}
+
 /* One cell update; see the file header for the five parts. */
 static void update_cell(orc_lbm *L, int x, int y, int z) {
     const size_t c = cidx(L, x, y, z);
@@ -191,17 +247,26 @@ static void update_cell(orc_lbm *L, int x, int y, int z) {
     for (int i = 0; i < Q; ++i) {
         int s[3];
         int beyond[3] = {0, 0, 0}; /* -1: beyond the low face, +1: beyond the high face */
-        int wall_link = 0;
+        int wall_link = 0, ofc = -1;
         for (int a = 0; a < 3; ++a) {
             s[a] = p[a] - E[i][a];
             if (s[a] < 0 || s[a] >= L->n[a]) {
-                if (L->wall[a]) {
+                const int face = 2 * a + (s[a] < 0 ? 0 : 1);
+                if (L->kind[face] == ORC_WALL) {
                     wall_link = 1;
                     beyond[a] = s[a] < 0 ? -1 : 1;
-                } else {
+                } else if (L->kind[face] == ORC_PERIODIC) {
                     s[a] = (s[a] + L->n[a]) % L->n[a]; /* periodic image */
+                } else {
+                    ofc = face; /* only x faces are open */
                 }
             }
+        }
+        if (!wall_link && ofc >= 0) {
+            /* boundary node beyond an open face; x_f next to it inside */
+            const int xf = ofc == 0 ? 0 : L->n[0] - 1;
+            f[i] = open_node(L, ofc, i, cidx(L, xf, s[1], s[2]));
+            continue;
         }
         if (!wall_link && L->solid[cidx(L, s[0], s[1], s[2])]) {
             /* obstacle link: half-way bounce-back from a resting wall */

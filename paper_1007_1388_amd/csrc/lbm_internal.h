@@ -73,8 +73,14 @@ constexpr uint32_t kSolidBit = 0x80000000u;
 
 struct GridGeom {
   int n[3];         // global nx, ny, nz
-  int wall[3];      // 1: walls on both faces of the axis
-  int moving[6];    // face has a nonzero wall velocity
+  int wall[3];      // 1: the axis is bounded (walls or open faces), 0: periodic
+  int fwall[6];     // face is a bounce-back wall
+  int moving[6];    // wall face with a nonzero wall velocity
+  int open[2];      // -x / +x face: 0 not open, 1 VELOCITY, 2 PRESSURE
+  double ob_u[2][3];  // prescribed velocity of an open face
+  double ob_drho[2];  // prescribed rho - rho0 of an open face
+  double rho0;        // reference density and g/2 (open faces rebuild the
+  double hg[3];       // velocity of a post-collision state)
 };
 
 // Where a Block's boundary value of direction i goes when the fused

@@ -11,6 +11,7 @@
 // 3 shifted BF16 (storage), arithmetic type C = double or float.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #include "lbm_internal.h"
 
@@ -210,6 +211,24 @@ __device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, co
   return cw;
 }
 
+// Open x faces (non-equilibrium extrapolation, Guo, Zheng and Shi 2002): the
+// boundary node beyond face `side`, next to a cell with moments (drho_f,
+// u_f) and post-collision value f*_q, holds f*_q + feq~_q(drho_b, u_b) -
+// feq~_q(drho_f, u_f).  VELOCITY: u_b prescribed, drho_b = drho_f, so
+//   w_q rho0 [3 e.(u_b - u_f) + 4.5 ((e.u_b)^2 - (e.u_f)^2) - 1.5 (u_b^2 - u_f^2)];
+// PRESSURE: drho_b prescribed, u_b = u_f, so w_q (drho_b - drho_f).
+__device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, double rho0, double drho_f,
+                                            double ufx, double ufy, double ufz) {
+  const double w = Wd(q);
+  if (g.open[side] == 2) return w * (g.ob_drho[side] - drho_f);
+  const double* ub = g.ob_u[side];
+  const double eb = EXd(q) * ub[0] + EYd(q) * ub[1] + EZd(q) * ub[2];
+  const double ef = EXd(q) * ufx + EYd(q) * ufy + EZd(q) * ufz;
+  const double bb = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+  const double ff = ufx * ufx + ufy * ufy + ufz * ufz;
+  return w * rho0 * (3.0 * (eb - ef) + 4.5 * (eb * eb - ef * ef) - 1.5 * (bb - ff));
+}
+
 // One wave updates a row segment: each lane owns VEC consecutive cells of a
 // row, xw lanes per row (the smallest power of two covering the row, at most
 // 64), 64/xw rows per wave, so the plane z and the first row y0w are uniform
@@ -380,12 +399,12 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // ---- update phase
   const int gx0 = B.org[0] + x0, gy = B.org[1] + y, gz = B.org[2] + z;
   WallFlags wf;
-  wf.lox = A.geo.wall[0] && gx0 == 0;
-  wf.hix = A.geo.wall[0] && gx0 + VEC - 1 == A.geo.n[0] - 1;
-  wf.loy = A.geo.wall[1] && gy == 0;
-  wf.hiy = A.geo.wall[1] && gy == A.geo.n[1] - 1;
-  wf.loz = A.geo.wall[2] && gz == 0;
-  wf.hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
+  wf.lox = A.geo.fwall[0] && gx0 == 0;
+  wf.hix = A.geo.fwall[1] && gx0 + VEC - 1 == A.geo.n[0] - 1;
+  wf.loy = A.geo.fwall[2] && gy == 0;
+  wf.hiy = A.geo.fwall[3] && gy == A.geo.n[1] - 1;
+  wf.loz = A.geo.fwall[4] && gz == 0;
+  wf.hiz = A.geo.fwall[5] && gz == A.geo.n[2] - 1;
   const bool moving = A.geo.moving[0] | A.geo.moving[1] | A.geo.moving[2] | A.geo.moving[3] | A.geo.moving[4] |
                       A.geo.moving[5];
 
@@ -766,6 +785,45 @@ __global__ void __launch_bounds__(256) k_linkmask(const uint8_t* __restrict__ so
   }
 }
 
+// Boundary nodes of open x faces next to cell (x, y, z) of B (global x gx):
+// from its stored post-collision populations (drho = sum f~,
+// u = sum e f~ / rho0 - g/2, the collision invariants), each population that
+// enters the domain through the face, f~_q + open_corr, into the x-ghost slot
+// of the cell's own row (an interior row: no wall bounce-back slot lies
+// there).  FP64 arithmetic.
+template <int PREC>
+__device__ __forceinline__ void open_fill(typename Stor<PREC>::T* grid, const GridGeom& geo, const BlockDev& B, int x,
+                                          int y, int z, int gx) {
+  using T = typename Stor<PREC>::T;
+  const bool lo = geo.open[0] && gx == 0, hi = geo.open[1] && gx == geo.n[0] - 1;
+  if (!(lo || hi)) return;
+  double f[kQ], d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int i = 0; i < kQ; ++i) {
+    f[i] = (double)to_c<PREC, double>(grid[main_off(B, i, x, y, z)]);
+    d += f[i];
+    jx += EXd(i) * f[i];
+    jy += EYd(i) * f[i];
+    jz += EZd(i) * f[i];
+  }
+  const double r0 = geo.rho0;
+  const double ux = jx / r0 - geo.hg[0], uy = jy / r0 - geo.hg[1], uz = jz / r0 - geo.hg[2];
+  // On a periodic y or z axis the node is also the periodic image of the
+  // ghost row beyond the opposite face (cell (0, 0, z) pulls e = (1, 1, 0)
+  // from (-1, -1, z) = (-1, ny - 1, z)); the Block spans the whole axis, so
+  // no exchange fills those rows, and no wall slot lies in them.
+  const int ny = B.dim[1], nz = B.dim[2];
+  const int y2 = !geo.wall[1] && y == ny - 1 ? -1 : (!geo.wall[1] && y == 0 ? ny : INT_MIN);
+  const int z2 = !geo.wall[2] && z == nz - 1 ? -1 : (!geo.wall[2] && z == 0 ? nz : INT_MIN);
+  for (int i = 1; i < kQ; ++i) {
+    if ((EXd(i) > 0 && lo) || (EXd(i) < 0 && hi)) {
+      const T v = from_c<PREC, double>(f[i] + open_corr(geo, EXd(i) > 0 ? 0 : 1, i, r0, d, ux, uy, uz));
+      grid[xg_off(B, i, y, z)] = v;
+      if (y2 != INT_MIN) grid[xg_off(B, i, y2, z)] = v;
+      if (z2 != INT_MIN) grid[xg_off(B, i, y, z2)] = v;
+    }
+  }
+}
+
 // Bounce-back slots of a state loaded from outside the sweep (rest state,
 // warm start, checkpoint): for every wall link of a fluid cell x, slot
 // (x - e_i, i) = f_ibar(x) + 6 w_i rho0 e_i.u_w, rounded as the sweep rounds
@@ -783,12 +841,12 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
     if (solid) return;
     const int gx = B.org[0] + x, gy = B.org[1] + y, gz = B.org[2] + z;
     WallFlags wf;
-    wf.lox = A.geo.wall[0] && gx == 0;
-    wf.hix = A.geo.wall[0] && gx == A.geo.n[0] - 1;
-    wf.loy = A.geo.wall[1] && gy == 0;
-    wf.hiy = A.geo.wall[1] && gy == A.geo.n[1] - 1;
-    wf.loz = A.geo.wall[2] && gz == 0;
-    wf.hiz = A.geo.wall[2] && gz == A.geo.n[2] - 1;
+    wf.lox = A.geo.fwall[0] && gx == 0;
+    wf.hix = A.geo.fwall[1] && gx == A.geo.n[0] - 1;
+    wf.loy = A.geo.fwall[2] && gy == 0;
+    wf.hiy = A.geo.fwall[3] && gy == A.geo.n[1] - 1;
+    wf.loz = A.geo.fwall[4] && gz == 0;
+    wf.hiz = A.geo.fwall[5] && gz == A.geo.n[2] - 1;
     for (int i = 1; i < kQ; ++i) {
       // walls only: obstacle links are bounced on the pull side of the sweep
       const bool bw = wall_link<1>(wf, i, 0);
@@ -803,7 +861,31 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
       if (moving && bw) v = from_c<PREC, C>(to_c<PREC, C>(v) + wall_corr<C, 1>(sa, ph, wf, i, 0));
       grid[o] = v;
     }
+    open_fill<PREC>(grid, A.geo, B, x, y, z, gx);
   });
+}
+
+// Open x faces, once per step after the sweep (and after a state is loaded):
+// the boundary nodes beyond the open faces from the grid just written.  One
+// thread per cell of the face (the Blocks on an open face span all of y and
+// z); the Blocks touching no open face have nothing to do.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_openfill(void* grid_, const BlockDev* __restrict__ blocks, int nblocks,
+                                                  GridGeom geo) {
+  using T = typename Stor<PREC>::T;
+  T* grid = (T*)grid_;
+  const int per_face = geo.n[1] * geo.n[2];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * per_face) return;
+  const int side = t / per_face, yz = t % per_face;
+  if (!geo.open[side]) return;
+  const int y = yz % geo.n[1], z = yz / geo.n[1];
+  const int gx = side == 0 ? 0 : geo.n[0] - 1;
+  for (int j = 0; j < nblocks; ++j) {
+    const BlockDev& B = blocks[j];
+    if (gx < B.org[0] || gx >= B.org[0] + B.dim[0]) continue;
+    open_fill<PREC>(grid, geo, B, gx - B.org[0], y, z, gx);
+  }
 }
 
 // f~ = feq~(rho - rho0, u) of Eq. (2) in FP64 (warm start), 0 in solid cells.
@@ -1046,6 +1128,17 @@ void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const 
       break;
     case 2: hipLaunchKernelGGL((k_bbfill<2, float>), g, b, 0, s, grid, a, pf); break;
     default: hipLaunchKernelGGL((k_bbfill<3, float>), g, b, 0, s, grid, a, pf); break;
+  }
+}
+
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo, hipStream_t s) {
+  const int n = 2 * geo.n[1] * geo.n[2];
+  const dim3 g((n + 255) / 256), b(256);
+  switch (prec) {
+    case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, geo); break;
+    case 1: hipLaunchKernelGGL(k_openfill<1>, g, b, 0, s, grid, blocks, nblocks, geo); break;
+    case 2: hipLaunchKernelGGL(k_openfill<2>, g, b, 0, s, grid, blocks, nblocks, geo); break;
+    default: hipLaunchKernelGGL(k_openfill<3>, g, b, 0, s, grid, blocks, nblocks, geo); break;
   }
 }
 

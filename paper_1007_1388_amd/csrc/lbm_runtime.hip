@@ -31,6 +31,7 @@ void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev*
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
                    const Phys<float>& pf, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo, hipStream_t s);
 void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const double* rho, const double* u,
                     long long N, hipStream_t s);
 void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, const double hg[3], double* rho,
@@ -408,9 +409,18 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
                cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
+bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
+
+// After the sweep into grid g: the ghost exchange (unless the sweep did it)
+// and the boundary nodes of open faces.
+void enqueue_post(lbm_ctx* c, int g, hipStream_t s) {
+  if (c->sched.fused_exchange != 1) enqueue_exchange(c, g, s, c->sched.fused_exchange == 2);
+  if (has_open(c)) launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->geo, s);
+}
+
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
   enqueue_sweep(c, from, s);
-  if (c->sched.fused_exchange != 1) enqueue_exchange(c, 1 - from, s, c->sched.fused_exchange == 2);
+  enqueue_post(c, 1 - from, s);
 }
 
 lbm_status capture(lbm_ctx* c, int from, int nsteps, hipGraphExec_t* out) {
@@ -590,24 +600,35 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
   if (p->precision < LBM_F64 || p->precision > LBM_BF16S) return fail(LBM_EINVAL, "bad precision");
   if (p->row_pad < -1 || p->row_pad > 64) return fail(LBM_EINVAL, "row_pad must be in [-1, 64]");
+  bool any_open = false;
   for (int k = 0; k < 3; ++k) {
     if (!std::isfinite(p->force[k])) return fail(LBM_EINVAL, "force must be finite");
     const int f0 = p->face[2 * k], f1 = p->face[2 * k + 1];
-    if ((f0 != LBM_PERIODIC && f0 != LBM_WALL) || f0 != f1)
-      return fail(LBM_EINVAL, "opposite faces must both be PERIODIC or both WALL");
+    for (const int fk : {f0, f1}) {
+      if (fk < LBM_PERIODIC || fk > LBM_PRESSURE) return fail(LBM_EINVAL, "bad face kind");
+      if ((fk == LBM_VELOCITY || fk == LBM_PRESSURE) && k != 0)
+        return fail(LBM_EINVAL, "VELOCITY and PRESSURE faces are x faces only");
+      any_open = any_open || fk == LBM_VELOCITY || fk == LBM_PRESSURE;
+    }
+    if ((f0 == LBM_PERIODIC) != (f1 == LBM_PERIODIC))
+      return fail(LBM_EINVAL, "PERIODIC faces come in opposite pairs");
   }
   for (int f = 0; f < 6; ++f) {
     const int axis = f / 2;
     for (int k = 0; k < 3; ++k) {
       const double v = p->wall_u[f][k];
       if (!std::isfinite(v)) return fail(LBM_EINVAL, "wall velocity must be finite");
-      if (v != 0.0 && (k == axis || p->face[f] == LBM_PERIODIC))
-        return fail(LBM_EINVAL, "wall velocity must be tangential and only on WALL faces");
+      if (v != 0.0 && p->face[f] != LBM_VELOCITY && (k == axis || p->face[f] != LBM_WALL))
+        return fail(LBM_EINVAL, "wall velocity must be tangential and only on WALL (or VELOCITY) faces");
     }
+    if (p->face[f] == LBM_PRESSURE && !(p->face_rho[f] > 0 && std::isfinite(p->face_rho[f])))
+      return fail(LBM_EINVAL, "a PRESSURE face needs a finite density > 0");
   }
   std::vector<int> cuts[3], owner;
   std::string err;
   if (!build_tiling(p->dims, blocks, nblocks, cuts, owner, err)) return fail(LBM_EINVAL, err);
+  if (any_open && (cuts[1].size() != 2 || cuts[2].size() != 2))
+    return fail(LBM_EINVAL, "open x faces need one Block across y and across z");
 
   lbm_ctx* c = new lbm_ctx();
   c->p = *p;
@@ -633,10 +654,20 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   // geometry and physics constants
   for (int k = 0; k < 3; ++k) {
     c->geo.n[k] = p->dims[k];
-    c->geo.wall[k] = p->face[2 * k] == LBM_WALL ? 1 : 0;
+    c->geo.wall[k] = p->face[2 * k] != LBM_PERIODIC ? 1 : 0;
   }
-  for (int f = 0; f < 6; ++f)
-    c->geo.moving[f] = (p->wall_u[f][0] != 0.0 || p->wall_u[f][1] != 0.0 || p->wall_u[f][2] != 0.0) ? 1 : 0;
+  for (int f = 0; f < 6; ++f) {
+    c->geo.fwall[f] = p->face[f] == LBM_WALL ? 1 : 0;
+    c->geo.moving[f] = c->geo.fwall[f] &&
+                       (p->wall_u[f][0] != 0.0 || p->wall_u[f][1] != 0.0 || p->wall_u[f][2] != 0.0);
+  }
+  c->geo.rho0 = p->rho0;
+  for (int k = 0; k < 3; ++k) c->geo.hg[k] = 0.5 * p->force[k];
+  for (int s = 0; s < 2; ++s) {
+    c->geo.open[s] = p->face[s] == LBM_VELOCITY ? 1 : (p->face[s] == LBM_PRESSURE ? 2 : 0);
+    for (int k = 0; k < 3; ++k) c->geo.ob_u[s][k] = p->face[s] == LBM_VELOCITY ? p->wall_u[s][k] : 0.0;
+    c->geo.ob_drho[s] = p->face[s] == LBM_PRESSURE ? p->face_rho[s] - p->rho0 : 0.0;
+  }
   const double omega = 1.0 / p->tau;
   c->phd.omega = omega;
   c->phd.rho0 = p->rho0;
@@ -831,6 +862,13 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
 
 lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (solid && (c->geo.open[0] || c->geo.open[1])) {
+    // the boundary node of an open face extrapolates from a fluid cell
+    const int nx = c->geo.n[0];
+    for (long long r = 0; r < c->n_cells / nx; ++r)
+      if ((c->geo.open[0] && solid[r * nx]) || (c->geo.open[1] && solid[r * nx + nx - 1]))
+        return fail(LBM_EINVAL, "solid cell on an open face");
+  }
   drop_graphs(c);
   bool any = false;
   long long nsolid = 0;
@@ -902,7 +940,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms) {
   if (!c || !sweep_ms || !exchange_ms) return fail(LBM_EINVAL, "NULL argument");
   if (n < 1 || n > 100000) return fail(LBM_EINVAL, "step count must be in [1, 100000]");
-  const bool ex = c->sched.fused_exchange != 1;
+  const bool ex = c->sched.fused_exchange != 1 || has_open(c);
   const size_t ne = (size_t)n * (ex ? 3 : 2);
   std::vector<hipEvent_t> ev(ne, nullptr);
   lbm_status st = LBM_OK;
@@ -916,7 +954,7 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* excha
       enqueue_sweep(c, c->cur, c->stream);
       (void)hipEventRecord(ev[k++], c->stream);
       if (ex) {
-        enqueue_exchange(c, 1 - c->cur, c->stream, c->sched.fused_exchange == 2);
+        enqueue_post(c, 1 - c->cur, c->stream);
         (void)hipEventRecord(ev[k++], c->stream);
       }
       c->cur = 1 - c->cur;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_EUNSTABLE = range(6)
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = range(4)
-LBM_PERIODIC, LBM_WALL = 0, 1
+LBM_PERIODIC, LBM_WALL, LBM_VELOCITY, LBM_PRESSURE = 0, 1, 2, 3
 PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 STORAGE_DTYPE = {LBM_F64: np.float64, LBM_F32: np.float32, LBM_F16S: np.uint16, LBM_BF16S: np.uint16}
 FACES = ("-x", "+x", "-y", "+y", "-z", "+z")
@@ -47,7 +47,8 @@ class lbm_params(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
                 ("precision", ctypes.c_int32), ("fp64_math", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", ctypes.c_void_p), ("row_pad", ctypes.c_int32)]
+                ("alloc_user", ctypes.c_void_p), ("row_pad", ctypes.c_int32),
+                ("face_rho", ctypes.c_double * 6)]
 
 
 class lbm_schedule(ctypes.Structure):
@@ -256,7 +257,11 @@ def lbm_bw_probe(dst_ptr, src_ptr, nbytes, reps, stream):
 # ----------------------------------------------------------- convenience ---
 
 def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.0,
-                force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False, stream=None, row_pad=0):
+                force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False, stream=None, row_pad=0,
+                open_x=None):
+    """open_x = {"-x" or "+x": ("velocity", (ux, uy, uz)) | ("pressure", rho) |
+    "wall"}: open x faces (non-equilibrium extrapolation); an x face not named
+    keeps what walls[0] says (which must then be True)."""
     p = lbm_params()
     p.dims[:] = [int(d) for d in dims]
     for k in range(3):
@@ -266,6 +271,19 @@ def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.
     for face, vel in (wall_u or {}).items():
         for a in range(3):
             p.wall_u[FACES.index(face)][a] = float(vel[a])
+    for face, spec in (open_x or {}).items():
+        k = {"-x": 0, "+x": 1}[face]
+        if spec == "wall":
+            p.face[k] = LBM_WALL
+        elif spec[0] == "velocity":
+            p.face[k] = LBM_VELOCITY
+            for a in range(3):
+                p.wall_u[k][a] = float(spec[1][a])
+        elif spec[0] == "pressure":
+            p.face[k] = LBM_PRESSURE
+            p.face_rho[k] = float(spec[1])
+        else:
+            raise ValueError("bad open face %r" % (spec,))
     p.tau = float(tau)
     p.rho0 = float(rho0)
     p.force[:] = [float(v) for v in force]
@@ -308,7 +326,7 @@ class Lattice:
 
     def __init__(self, dims, blocks=None, walls=(False, False, False), wall_u=None, tau=0.6,
                  rho0=1.0, force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False,
-                 stream=None, torch_alloc=True, row_pad=0):
+                 stream=None, torch_alloc=True, row_pad=0, open_x=None):
         load()
         import torch
         if not torch.cuda.is_available():
@@ -324,7 +342,7 @@ class Lattice:
             blocks = [((0, 0, 0), self.dims)]
         self.blocks = [tuple(map(tuple, b)) for b in blocks]
         self.params = make_params(dims, walls, wall_u, tau, rho0, force, precision, fp64_math, stream,
-                                  row_pad)
+                                  row_pad, open_x)
         self._alloc = None
         if torch_alloc:
             self._alloc = _TorchAllocator(stream)

@@ -9,10 +9,13 @@
    until the residual ||u^n - u^(n-2)|| / (2 ||u^n||) drops below 1e-6.
 2. Training: the U-Net of surrogate.py on (mask, g_x) -> (u, rho - rho0)/g_x,
    BF16 MFMA kernels, FP32 master weights, Adam, masked MSE on fluid cells.
-3. Evaluation on M held-out seeds: steps and wall time to residual 1e-6 from
-   rest and from the network's prediction (inference included), the
-   difference of the two converged fields, and the distance of each from a
-   tightly converged FP64 reference (two-step residual 1e-10).
+3. Evaluation on M held-out seeds against a tightly converged FP64 reference
+   (two-step residual 1e-10): steps and time from rest and from the network's
+   prediction (inference included) to the residual criterion 1e-6, and to
+   velocity errors of 1e-2, 3e-3, 1e-3 and 3e-4 against the reference.  The
+   residual criterion alone flatters the warm start: it stops a run whose
+   remaining error decays slowly, and a warm-started run can stop farther
+   from the steady state than one from rest.
 
 The solver judges the network: a prediction only sets the initial state, and
 both runs stop on the same residual criterion of the same solver.
@@ -175,8 +178,11 @@ class Trainer:
                 assert st == 0
                 net.zero_grad()
                 net.backward(dpred)
-                # cosine learning-rate decay
-                lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / max(1, total)))
+                # linear warm-up over the first 5 % of the steps (Adam's
+                # first updates at the full rate can throw the network into a
+                # poor region), then cosine decay
+                warm = max(100, total // 20)
+                lr_t = lr * min(1.0, (it + 1) / warm) * 0.5 * (1 + math.cos(math.pi * it / max(1, total)))
                 net.adam(lr_t)
                 it += 1
             torch.cuda.synchronize()
@@ -210,8 +216,72 @@ class Trainer:
         return rho, u
 
 
+TARGETS = (1e-2, 3e-3, 1e-3, 3e-4)
+
+
+def reference(gx, solid, tol=1e-10, max_steps=400_000):
+    """Tightly converged steady velocity (device, FP64 storage): from rest to
+    a two-step residual of `tol`, averaged over two consecutive steps (which
+    removes any period-two part); returns (u, steps, residual)."""
+    lat = make_lattice(gx, solid, None, precision="f64")
+    (n, _, r), = run_to_steady([lat], max_steps=max_steps, tol=tol)
+    _, ua = lat.macroscopic_device()
+    lat.step(1)
+    _, ub = lat.macroscopic_device()
+    import torch
+    torch.cuda.synchronize()
+    lat.close()
+    return 0.5 * (ua + ub), n, r
+
+
+def converge_tracked(lat, u_ref, fluid, check_every=100, max_steps=60_000):
+    """Step `lat` until its two-step residual is below TOL and its velocity is
+    within the smallest of TARGETS of u_ref (relative 2-norm over fluid
+    cells), checking every `check_every` steps.  The error is taken both of
+    the velocity itself and of its average over the last two steps: a
+    period-two oscillation that bounce-back sustains in some pore geometries
+    (and that the two-step residual cannot see) shows only in the first.
+    Returns (steps to residual TOL, {target: steps} for the velocity,
+    {target: steps} for the two-step average, seconds per step of the
+    stepping and residual work alone, final errors (velocity, average))."""
+    import torch
+    nref = torch.linalg.vector_norm(u_ref[:, fluid])
+    hit, hit2, n_res, steps, t_steps = {}, {}, None, 0, 0.0
+    err = err2 = float("nan")
+    while steps < max_steps:
+        t = time.perf_counter()
+        lat.step(check_every - 3)
+        lat.residual_mark()
+        lat.step(2)
+        r2, m = lat.residual_since_mark()
+        t_steps += time.perf_counter() - t
+        _, ua = lat.macroscopic_device()
+        t = time.perf_counter()
+        lat.step(1)
+        torch.cuda.synchronize()
+        t_steps += time.perf_counter() - t
+        _, u = lat.macroscopic_device()
+        torch.cuda.synchronize()
+        steps += check_every
+        r = r2 / m
+        if n_res is None and r < TOL:
+            n_res = steps
+        err = float(torch.linalg.vector_norm((u - u_ref)[:, fluid]) / nref)
+        err2 = float(torch.linalg.vector_norm((0.5 * (u + ua) - u_ref)[:, fluid]) / nref)
+        for tg in TARGETS:
+            if tg not in hit and err < tg:
+                hit[tg] = steps
+            if tg not in hit2 and err2 < tg:
+                hit2[tg] = steps
+        if (n_res is not None and len(hit) == len(TARGETS) and len(hit2) == len(TARGETS)) or not math.isfinite(r):
+            break
+    return n_res, hit, hit2, t_steps / max(steps, 1), (err, err2)
+
+
 def evaluate(trainer, seeds, log=print):
-    """Time to residual 1e-6 from rest and from the prediction, per seed."""
+    """Per held-out seed: steps and time from rest and from the network's
+    prediction (inference included) to the residual criterion, and to each
+    accuracy target against a tightly converged FP64 reference."""
     import torch
     rows = []
     nx, ny, nz = DIMS
@@ -219,54 +289,75 @@ def evaluate(trainer, seeds, log=print):
     for s in seeds:
         solid, gx, frac = sample(s)
         d = dict(solid=torch.from_numpy(solid.reshape(-1)).cuda(), gx=gx)
+        fluid = torch.from_numpy(solid == 0).cuda()
+        u_ref, n_ref, r_ref = reference(gx, solid)
         # from rest
         torch.cuda.synchronize()
         lat = make_lattice(gx, solid, None)
-        (n0, t0, r0), = run_to_steady([lat])
-        rho0_, u0_ = lat.macroscopic()
+        n0, hit0, avg0, sps0, e0 = converge_tracked(lat, u_ref, fluid)
         lat.close()
-        # warm start: inference + initial state + solve, all timed
+        # warm start: inference and initial state timed
         torch.cuda.synchronize()
         t_a = time.perf_counter()
         rho_p, u_p = trainer.predict(d)
         lat = make_lattice(gx, solid, None)
         lat.set_equilibrium(rho_p.cpu().numpy().reshape(shape), u_p.cpu().numpy().reshape((3,) + shape))
+        torch.cuda.synchronize()
         t_inf = time.perf_counter() - t_a
-        (n1, t1, r1), = run_to_steady([lat])
-        rho1_, u1_ = lat.macroscopic()
+        n1, hit1, avg1, sps1, e1 = converge_tracked(lat, u_ref, fluid)
         lat.close()
-        t1 += t_inf
-        # tightly converged reference: FP64 storage, continued from the
-        # rest solution to a two-step residual of 1e-10
-        lat = make_lattice(gx, solid, None, precision="f64")
-        lat.set_equilibrium(rho0_, u0_)
-        (n2, _, r2), = run_to_steady([lat], max_steps=200_000, tol=1e-10)
-        _, u2_ = lat.macroscopic()
-        lat.close()
-        fluid = solid == 0
-        ref = u0_[:, fluid]
-        tight = u2_[:, fluid]
-        nt = np.linalg.norm(tight)
-        diff = np.linalg.norm(u1_[:, fluid] - ref) / np.linalg.norm(ref)
-        pred_err = np.linalg.norm(u_p.cpu().numpy().reshape((3,) + shape)[:, fluid] - ref) / np.linalg.norm(ref)
-        rows.append(dict(seed=s, gx=gx, solid_frac=frac, steps_rest=n0, secs_rest=t0, steps_warm=n1, secs_warm=t1,
-                         infer_secs=t_inf, final_diff=diff, pred_err=pred_err, ref_steps=n2, ref_resid=r2,
-                         dist_rest=float(np.linalg.norm(ref - tight) / nt),
-                         dist_warm=float(np.linalg.norm(u1_[:, fluid] - tight) / nt)))
-        log("seed %d: rest %d steps %.3fs, warm %d steps %.3fs (pred err %.3e, final diff %.2e, to the tight "
-            "reference: rest %.2e warm %.2e)" % (s, n0, t0, n1, t1, pred_err, diff, rows[-1]["dist_rest"],
-                                                rows[-1]["dist_warm"]))
+        nref = torch.linalg.vector_norm(u_ref[:, fluid])
+        pred_err = float(torch.linalg.vector_norm((u_p.reshape((3,) + shape) - u_ref)[:, fluid]) / nref)
+        row = dict(seed=s, gx=gx, solid_frac=frac, ref_steps=n_ref, ref_resid=r_ref, infer_secs=t_inf,
+                   pred_err=pred_err, sps_rest=sps0, sps_warm=sps1, err_end_rest=e0[0], err_end_warm=e1[0],
+                   avgerr_end_rest=e0[1], avgerr_end_warm=e1[1],
+                   steps_rest=n0, steps_warm=n1,
+                   secs_rest=None if n0 is None else n0 * sps0,
+                   secs_warm=None if n1 is None else t_inf + n1 * sps1)
+        for tg in TARGETS:
+            k = "%.0e" % tg
+            row["steps_rest_" + k] = hit0.get(tg)
+            row["steps_warm_" + k] = hit1.get(tg)
+            row["secs_rest_" + k] = None if tg not in hit0 else hit0[tg] * sps0
+            row["secs_warm_" + k] = None if tg not in hit1 else t_inf + hit1[tg] * sps1
+            row["steps_rest_avg_" + k] = avg0.get(tg)
+            row["steps_warm_avg_" + k] = avg1.get(tg)
+            row["secs_rest_avg_" + k] = None if tg not in avg0 else avg0[tg] * sps0
+            row["secs_warm_avg_" + k] = None if tg not in avg1 else t_inf + avg1[tg] * sps1
+        rows.append(row)
+        log("seed %d: pred err %.3f; residual 1e-6: rest %s warm %s steps; to error 1e-3: rest %s warm %s steps "
+            "(two-step average: rest %s warm %s); final errors rest %.1e/%.1e warm %.1e/%.1e; inference %.1f ms"
+            % (s, pred_err, n0, n1, hit0.get(1e-3), hit1.get(1e-3), avg0.get(1e-3), avg1.get(1e-3), e0[0], e0[1],
+               e1[0], e1[1], 1e3 * t_inf))
     return rows
 
 
 def summarize(rows):
     def q(key):
-        v = np.array([r[key] for r in rows], dtype=float)
-        return dict(median=float(np.median(v)), q25=float(np.percentile(v, 25)), q75=float(np.percentile(v, 75)))
-    return dict(n=len(rows), steps_rest=q("steps_rest"), steps_warm=q("steps_warm"), secs_rest=q("secs_rest"),
-                secs_warm=q("secs_warm"), pred_err=q("pred_err"), final_diff=q("final_diff"),
-                dist_rest=q("dist_rest"), dist_warm=q("dist_warm"), ref_steps=q("ref_steps"),
-                speedup_median=float(np.median([r["secs_rest"] / r["secs_warm"] for r in rows])))
+        v = np.array([r[key] for r in rows if r[key] is not None], dtype=float)
+        if v.size == 0:
+            return None
+        return dict(median=float(np.median(v)), q25=float(np.percentile(v, 25)),
+                    q75=float(np.percentile(v, 75)), n=int(v.size))
+
+    def speedup(kr, kw):
+        v = [r[kr] / r[kw] for r in rows if r[kr] is not None and r[kw] is not None]
+        return float(np.median(v)) if v else None
+    out = dict(n=len(rows), pred_err=q("pred_err"), ref_steps=q("ref_steps"), infer_secs=q("infer_secs"),
+               steps_rest=q("steps_rest"), steps_warm=q("steps_warm"), secs_rest=q("secs_rest"),
+               secs_warm=q("secs_warm"), speedup_residual=speedup("secs_rest", "secs_warm"))
+    for tg in TARGETS:
+        k = "%.0e" % tg
+        out["steps_rest_" + k] = q("steps_rest_" + k)
+        out["steps_warm_" + k] = q("steps_warm_" + k)
+        out["speedup_" + k] = speedup("secs_rest_" + k, "secs_warm_" + k)
+        out["steps_rest_avg_" + k] = q("steps_rest_avg_" + k)
+        out["steps_warm_avg_" + k] = q("steps_warm_avg_" + k)
+        out["speedup_avg_" + k] = speedup("secs_rest_avg_" + k, "secs_warm_avg_" + k)
+    out["err_end_warm"] = q("err_end_warm")
+    out["avgerr_end_warm"] = q("avgerr_end_warm")
+    out["err_end_rest"] = q("err_end_rest")
+    return out
 
 
 def main():

@@ -89,6 +89,20 @@ def test_mismatched_faces_and_normal_wall_velocity_rejected():
     assert _status(p, BOX) == lbm.LBM_EINVAL
 
 
+def test_open_face_rules_rejected():
+    ok = dict(open_x={"-x": ("velocity", (0.01, 0, 0)), "+x": ("pressure", 1.0)})
+    p = lbm.make_params((8, 8, 8), walls=(True, False, True), tau=0.7, **ok)
+    p.face[2] = p.face[3] = lbm.LBM_VELOCITY          # open faces are x faces only
+    assert _status(p, BOX) == lbm.LBM_EINVAL
+    p = lbm.make_params((8, 8, 8), walls=(True, False, True), tau=0.7, open_x={"+x": ("pressure", 0.0)})
+    assert _status(p, BOX) == lbm.LBM_EINVAL            # density must be > 0
+    p = lbm.make_params((8, 8, 8), walls=(False, False, True), tau=0.7, open_x={"-x": ("pressure", 1.0)})
+    assert _status(p, BOX) == lbm.LBM_EINVAL            # periodic faces come in pairs
+    p = lbm.make_params((8, 8, 8), walls=(True, False, True), tau=0.7, **ok)
+    two_y = [((0, 0, 0), (8, 4, 8)), ((0, 4, 0), (8, 8, 8))]
+    assert _status(p, two_y) == lbm.LBM_EINVAL          # one Block across y and z
+
+
 @pytest.mark.parametrize("blocks", [
     [((0, 0, 0), (8, 8, 4))],                                   # does not cover
     [((0, 0, 0), (8, 8, 8)), ((0, 0, 0), (8, 8, 8))],           # overlap

@@ -33,6 +33,23 @@ def periodic_box(dims=(11, 9, 7), seed=1, force=(3e-5, -1e-5, 2e-5), tau=0.7):
     return dict(dims=dims, walls=(False, False, False), tau=tau, force=force, init=(rho, u))
 
 
+def duct(dims=(29, 10, 9), tau=0.7, force=(0.0, 3e-6, 0.0), seed=3, obstacles=True):
+    """Open x faces: velocity inlet with a tangential part at -x, pressure
+    outlet at +x, walls in z (the -z wall moving), periodic y, spheres off the
+    open faces, a perturbed warm start."""
+    solid = None
+    if obstacles:
+        solid = inputs.porous_spheres(dims, target_fraction=0.08, radius=(2, 3), seed=seed)
+        solid[:, :, 0] = 0
+        solid[:, :, -1] = 0
+    rho, u = inputs.perturbed_fields(dims, seed=seed, drho=1e-3, du=1e-2)
+    if solid is not None:
+        u[:, solid == 1] = 0.0
+    return dict(dims=dims, walls=(True, False, True), wall_u={"-z": (0.01, 0.0, 0.0)}, tau=tau, force=force,
+                open_x={"-x": ("velocity", (0.03, 0.005, 0.0)), "+x": ("pressure", 1.001)},
+                init=(rho, u), solid=solid)
+
+
 def run_gpu(case, steps, blocks=None, precision="f64", fp64_math=False, schedule=None):
     lat = gpu_lattice(case, blocks=blocks, precision=precision, fp64_math=fp64_math)
     if schedule:
@@ -182,6 +199,65 @@ def test_self_wrapping_periodic_box_matches_oracle():
     check_vs_oracle(lat, o, TOL["f64"])
     two = run_gpu(case, 30, blocks=inputs.uniform_blocks((70, 9, 7), (2, 1, 1)))
     assert np.array_equal(lat.get_state(as_fp64=False), two.get_state(as_fp64=False))
+
+
+# ------------------------------------------------- open faces (NEXT) -------
+
+@pytest.mark.parametrize("steps", [0, 1, 150])
+def test_open_faces_f64_match_oracle(steps):
+    """Velocity inlet and pressure outlet (non-equilibrium extrapolation) with
+    a moving wall, a body force, obstacles and a warm start, against the
+    oracle; steps = 1 checks the boundary nodes filled from a loaded state."""
+    case = duct()
+    lat = run_gpu(case, steps)
+    o = run_oracle(case, steps)
+    check_vs_oracle(lat, o, TOL["f64"])
+
+
+@pytest.mark.parametrize("fp64_math", [False, True])
+def test_open_faces_f32_storage(fp64_math):
+    case = duct()
+    lat = run_gpu(case, 150, precision="f32", fp64_math=fp64_math)
+    o = run_oracle(case, 150)
+    rho_g, u_g = lat.macroscopic()
+    rho_o, u_o = o.macroscopic()
+    err = field_errors(rho_g, u_g, rho_o, u_o)
+    assert err["u_inf"] <= TOL["f32"] and err["drho_inf"] <= TOL["f32"], err
+
+
+@pytest.mark.parametrize("variant", range(5))
+def test_open_faces_tilings_and_schedules_bitwise(variant):
+    """Blocks cut along x, every exchange mode and graph capture give the
+    one-Block result bit for bit; a row longer than a wave (y wraps on the
+    Block itself) with the open faces."""
+    dims = (70, 6, 5) if variant == 4 else (29, 10, 9)
+    case = duct(dims=dims, obstacles=variant != 4)
+    blocks = [None, inputs.uniform_blocks(dims, (3, 1, 1)),
+              [((0, 0, 0), (5, dims[1], dims[2])), ((5, 0, 0), (23, dims[1], dims[2])),
+               ((23, 0, 0), (dims[0], dims[1], dims[2]))],
+              inputs.uniform_blocks(dims, (2, 1, 1)), None][variant]
+    sched = [dict(fused_exchange=1), dict(fused_exchange=0), dict(fused_exchange=2),
+             dict(fused_exchange=1, graph_steps=4), dict(graph_steps=5)][variant]
+    ref = run_gpu(case, 37, precision="f32")
+    lat = run_gpu(case, 37, blocks=blocks, precision="f32", schedule=sched)
+    assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+    if variant == 4:
+        o = run_oracle(case, 37)
+        f64 = run_gpu(case, 37)
+        check_vs_oracle(f64, o, TOL["f64"])
+
+
+def test_open_faces_reject_solid_on_the_face():
+    case = duct(obstacles=False)
+    lat = gpu_lattice(case)
+    solid = np.zeros(lat.shape, np.uint8)
+    solid[3, 4, 0] = 1
+    from paper_1007_1388_amd import lbm
+    with pytest.raises(lbm.LBMError):
+        lat.set_geometry(solid)
+    solid[3, 4, 0] = 0
+    solid[3, 4, 5] = 1
+    lat.set_geometry(solid)
 
 
 SCHEDULES = [

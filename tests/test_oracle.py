@@ -170,6 +170,44 @@ def test_poiseuille_exact_discrete_profile(tau):
     assert np.abs(u[1:]).max() < 1e-13 * ref.max()
 
 
+@pytest.mark.parametrize("tau,steps", [(0.6, 60000), (0.8, 30000), (1.2, 20000)])
+def test_open_pressure_faces_give_the_exact_channel_flow(tau, steps):
+    # Pressure faces at both ends of a walled channel (non-equilibrium
+    # extrapolation, Guo, Zheng and Shi 2002) plus a body force.  The
+    # incompressible model's steady state is exact here: density linear in x
+    # between the boundary nodes one cell outside the faces (x = -1 and
+    # x = nx), and the force-driven Poiseuille profile of the test above with
+    # the pressure gradient added to the force, -dp/dx / rho0 = D / (3 (nx+1)),
+    # the same at every x (next to the faces too, where the corner links
+    # bounce back from the walls).
+    nx, nz, D, g = 20, 10, 1e-5, 2e-7
+    o = oracle.OracleLBM((nx, 1, nz), walls=(True, False, True), tau=tau, force=(g, 0, 0),
+                         open_x={"-x": ("pressure", 1.0 + D), "+x": ("pressure", 1.0)})
+    o.step(steps)
+    rho, u = o.macroscopic()
+    z, x = np.arange(nz), np.arange(nx)
+    K = 3 * (g + D / (3 * (nx + 1))) / (2 * tau - 1)
+    ref = K * (z + 0.5) * (nz - 0.5 - z) + K * (16 * tau * tau - 16 * tau + 1) / 12
+    assert np.abs(u[0][:, 0, :] - ref[:, None]).max() < 1e-10 * ref.max()
+    assert np.abs(rho[:, 0, :] - (1.0 + D * (nx - x) / (nx + 1))[None, :]).max() < 1e-9 * D
+    assert np.abs(u[1:]).max() < 1e-7 * ref.max()
+
+
+def test_open_velocity_inlet_and_pressure_outlet_reach_uniform_flow():
+    # Velocity inlet (with a tangential part) and pressure outlet around a
+    # frictionless periodic duct: from rest the flow must settle to the
+    # uniform state u = u_in, rho = rho_out, which is a fixed point of the
+    # extrapolation rule and the only steady state.
+    uin, rout = (0.02, 0.004, 0.0), 1.002
+    o = oracle.OracleLBM((12, 1, 1), walls=(True, False, False), tau=0.8,
+                         open_x={"-x": ("velocity", uin), "+x": ("pressure", rout)})
+    o.step(8000)
+    rho, u = o.macroscopic()
+    for a in range(3):
+        assert np.abs(u[a] - uin[a]).max() < 1e-12
+    assert np.abs(rho - rout).max() < 1e-12
+
+
 def test_couette_exact_linear_profile():
     # Moving +z wall, resting -z wall: the steady profile is linear with the
     # no-slip points half a cell outside the fluid (half-way bounce-back,

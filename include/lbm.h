@@ -71,8 +71,8 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_preci
  * prescribes u_b = wall_u[face] and takes drho_b = drho_f; PRESSURE
  * prescribes rho_b = face_rho[face] and takes u_b = u_f.  A link whose
  * source lies beyond a WALL face as well bounces back (walls take
- * precedence).  Open faces need one Block across y and across z, and no
- * solid cell on the face. */
+ * precedence).  Open faces need nx >= 2, one Block across y and across z,
+ * and no solid cell on the face; their contexts run one cell per lane. */
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_VELOCITY = 2, LBM_PRESSURE = 3 } lbm_face;
 
 /* Half-open global cell box [lo, hi) of one Block (the Block AABB, Sec. 4.2). */
@@ -121,8 +121,8 @@ typedef struct {
   int32_t nontemporal;     /* 1: streaming (non-temporal) loads and stores */
   int32_t cells_per_lane;  /* cells per lane along x: 0 = automatic (1); 1; or 2 (only for
                               F16S/BF16S and for F32 storage with FP64 arithmetic, with
-                              every Block's x extent even, else LBM_EINVAL).  Results do
-                              not depend on it. */
+                              every Block's x extent even and no open face, else
+                              LBM_EINVAL).  Results do not depend on it. */
 } lbm_schedule;
 
 typedef struct {
@@ -160,15 +160,17 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid);
 lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u);
 
 /* Enqueue n >= 0 time steps (each: stream-collide sweep over all Blocks plus
- * the ghost exchange) on the context stream.  Asynchronous. */
+ * the ghost exchange, and with open faces the fill of their boundary nodes)
+ * on the context stream.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
 
 /* Advances n steps (1 <= n <= 100000) exactly as lbm_step does, launched one
  * by one (no graphs), with a HIP event pair around every sweep launch and
- * every separate ghost-exchange launch on params.stream; returns the mean
- * duration of one sweep launch and of one exchange launch (0 when the
- * exchange is fused into the sweep), in milliseconds: the per-kernel
- * durations that bandwidth accounting divides by.  Synchronises. */
+ * the work after it (the separate ghost exchange and, with open faces, the
+ * boundary-node fill) on params.stream; returns the mean duration of one
+ * sweep launch and of the work after it (0 when the exchange is fused into
+ * the sweep and no face is open), in milliseconds: the per-kernel durations
+ * that bandwidth accounting divides by.  Synchronises. */
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms);
 
 /* Density and velocity used by the most recent collision (before any step:

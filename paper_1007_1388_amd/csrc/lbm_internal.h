@@ -128,6 +128,9 @@ struct SweepArgs {
   const ItemDev* items;
   const uint32_t* mask;
   const GhostTgt* ghost;  // [block][27]
+  double* side;           // open x faces: per face cell its 5 entering post-collision
+                          // populations and drho, u, padded to 16 ([face][nz][ny][16]);
+                          // NULL without
   int nitems;
   int pad;
   GridGeom geo;

@@ -253,7 +253,7 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 // every wall link; with FUSED the boundary values also go
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
                                           int z, int y0w, int seg, int yend, int xw, const GhostTgt* gts) {
   using T = typename Stor<PREC>::T;
@@ -533,6 +533,47 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     xpf = Gp.Sf;
   }
   const uint32_t roff = (uint32_t)(r * (int)sizeof(T));
+  // open x faces (OPEN variants only): the cell on the face keeps its
+  // moments and the populations that enter the domain through the face in a
+  // compact buffer, one 128-byte line per face cell written whole (9 values
+  // and zeros; a line written in part would cost the memory a
+  // read-modify-write), from which k_openfill writes the boundary nodes after
+  // the sweep: plain stores of values at hand, the boundary arithmetic stays
+  // out of the sweep.  With open faces a lane holds one cell and nx >= 2, so
+  // at most one face cell.
+  double* sp = nullptr;
+  int sdir = 0;  // e_x of the populations that enter through the lane's face
+  if (OPEN && A.side != nullptr) {
+    const long long cell = (long long)gz * A.geo.n[1] + gy;
+    if (A.geo.open[0] && gx0 == 0) {
+      sp = A.side + 16 * cell;
+      sdir = 1;
+    } else if (A.geo.open[1] && gx0 + VEC - 1 == A.geo.n[0] - 1) {
+      sp = A.side + 16 * ((long long)A.geo.n[1] * A.geo.n[2] + cell);
+      sdir = -1;
+    }
+  }
+  auto side_pop = [&](int q, const T (&o)[VEC]) {
+    if (OPEN && sdir != 0 && EXd(q) == sdir) {
+      const int slot = EXd(q) > 0 ? (q == 1 ? 0 : (q - 5) / 2) : (q == 2 ? 0 : (q - 6) / 2);
+      sp[slot] = (double)to_c<PREC, C>(sdir > 0 ? o[0] : o[VEC - 1]);
+    }
+  };
+  if (OPEN && sdir != 0) {
+    const int k = sdir > 0 ? 0 : VEC - 1;
+    sp[5] = (double)drho[k];
+    if constexpr (HYB) {
+      sp[6] = dux[k];
+      sp[7] = duy[k];
+      sp[8] = duz[k];
+    } else {
+      sp[6] = (double)ux[k];
+      sp[7] = (double)uy[k];
+      sp[8] = (double)uz[k];
+    }
+#pragma unroll
+    for (int j = 9; j < 16; ++j) sp[j] = 0.0;
+  }
   const bool rowok = FX != 2 || (y != 0 && y != b - 1 && z != 0 && z != c - 1);
   const bool send_lo = xm_on && x0 == 0 && rowok;
   const bool send_hi = xp_on && x0 + VEC - 1 == a - 1 && rowok;
@@ -605,6 +646,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       xface(i, o0);
       xface(i + 1, o1);
     }
+    if (OPEN && EXd(i) != 0) {
+      side_pop(i, o0);
+      side_pop(i + 1, o1);
+    }
   }
   if constexpr (FUSED) {
     // Waves with a row on a y or z face: the lane re-reads the values it has
@@ -638,7 +683,8 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 }
 
 // At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
+// OPEN: contexts with open x faces (one cell per lane).
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
 k_sweep(const SweepArgs A, const Phys<C> ph) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -664,7 +710,8 @@ k_sweep(const SweepArgs A, const Phys<C> ph) {
     const int yend = item.y0 + item.nrows;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FX, NT, VEC>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw, gts);
+      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw,
+                                                  gts);
     }
   }
 }
@@ -865,26 +912,38 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
   });
 }
 
-// Open x faces, once per step after the sweep (and after a state is loaded):
-// the boundary nodes beyond the open faces from the grid just written.  One
-// thread per cell of the face (the Blocks on an open face span all of y and
-// z); the Blocks touching no open face have nothing to do.
+// Open x faces, once per step after the sweep: the boundary nodes beyond the
+// open faces from the face cells' moments and entering populations that the
+// sweep left in `side` (the moments of their collision, as the boundary rule
+// asks).  One thread per face cell, consecutive threads consecutive y.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_openfill(void* grid_, const BlockDev* __restrict__ blocks, int nblocks,
-                                                  GridGeom geo) {
+                                                  GridGeom geo, const double* __restrict__ side) {
   using T = typename Stor<PREC>::T;
   T* grid = (T*)grid_;
-  const int per_face = geo.n[1] * geo.n[2];
+  const int ny = geo.n[1], nz = geo.n[2];
+  const int per_face = ny * nz;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * per_face) return;
-  const int side = t / per_face, yz = t % per_face;
-  if (!geo.open[side]) return;
-  const int y = yz % geo.n[1], z = yz / geo.n[1];
-  const int gx = side == 0 ? 0 : geo.n[0] - 1;
-  for (int j = 0; j < nblocks; ++j) {
-    const BlockDev& B = blocks[j];
-    if (gx < B.org[0] || gx >= B.org[0] + B.dim[0]) continue;
-    open_fill<PREC>(grid, geo, B, gx - B.org[0], y, z, gx);
+  const int f = t / per_face, yz = t % per_face;
+  if (!geo.open[f]) return;
+  const int y = yz % ny, z = yz / ny;
+  const int gx = f == 0 ? 0 : geo.n[0] - 1;
+  int j = 0;
+  while (j < nblocks && !(gx >= blocks[j].org[0] && gx < blocks[j].org[0] + blocks[j].dim[0])) ++j;
+  if (j == nblocks) return;
+  const BlockDev& B = blocks[j];
+  const double* cs = side + 16 * ((long long)f * per_face + yz);
+  auto at = [&](int slot) { return cs[slot]; };
+  const double d = at(5), ux = at(6), uy = at(7), uz = at(8);
+  const int y2 = !geo.wall[1] && y == ny - 1 ? -1 : (!geo.wall[1] && y == 0 ? ny : INT_MIN);
+  const int z2 = !geo.wall[2] && z == nz - 1 ? -1 : (!geo.wall[2] && z == 0 ? nz : INT_MIN);
+  for (int slot = 0; slot < 5; ++slot) {
+    const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
+    const T v = from_c<PREC, double>(at(slot) + open_corr(geo, f, q, geo.rho0, d, ux, uy, uz));
+    grid[xg_off(B, q, y, z)] = v;
+    if (y2 != INT_MIN) grid[xg_off(B, q, y2, z)] = v;
+    if (z2 != INT_MIN) grid[xg_off(B, q, y, z2)] = v;
   }
 }
 
@@ -1063,12 +1122,28 @@ __global__ void __launch_bounds__(256) k_copy16(const u32x4* __restrict__ src, u
 // ------------------------------------------------------------- launchers
 using SweepFn = void (*)(SweepArgs, Phys<double>, Phys<float>, dim3, dim3, hipStream_t);
 
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN = false>
 static void launch_sweep_t(SweepArgs a, Phys<double> pd, Phys<float> pf, dim3 g, dim3 b, hipStream_t s) {
   if constexpr (sizeof(C) == 8)
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC>), g, b, 0, s, a, pd);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN>), g, b, 0, s, a, pd);
   else
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC>), g, b, 0, s, a, pf);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN>), g, b, 0, s, a, pf);
+}
+
+// Contexts with open faces: one cell per lane, non-temporal (the cache hint
+// changes no result).
+template <int PREC, typename C>
+static SweepFn pick_open(bool mask, int fx) {
+#define LBM_PICK(M, F) return launch_sweep_t<PREC, C, M, F, true, 1, true>
+  if (mask) {
+    if (fx == 1) LBM_PICK(true, 1);
+    if (fx == 2) LBM_PICK(true, 2);
+    LBM_PICK(true, 0);
+  }
+  if (fx == 1) LBM_PICK(false, 1);
+  if (fx == 2) LBM_PICK(false, 2);
+  LBM_PICK(false, 0);
+#undef LBM_PICK
 }
 
 template <int PREC, typename C, int VEC>
@@ -1094,6 +1169,16 @@ void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, c
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
   const bool v = vec == 2 && sweep_vec2_ok(prec, f64math);
+  if (a.side != nullptr) {
+    switch (prec) {
+      case 0: fn = pick_open<0, double>(mask, fx); break;
+      case 1: fn = f64math ? pick_open<1, double>(mask, fx) : pick_open<1, float>(mask, fx); break;
+      case 2: fn = pick_open<2, float>(mask, fx); break;
+      default: fn = pick_open<3, float>(mask, fx); break;
+    }
+    fn(a, pd, pf, grid, block, s);
+    return;
+  }
   switch (prec) {
     case 0: fn = pick3<0, double, 1>(mask, fx, nt); break;
     case 1:
@@ -1131,14 +1216,15 @@ void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const 
   }
 }
 
-void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo, hipStream_t s) {
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo,
+                     const double* side, hipStream_t s) {
   const int n = 2 * geo.n[1] * geo.n[2];
   const dim3 g((n + 255) / 256), b(256);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, geo); break;
-    case 1: hipLaunchKernelGGL(k_openfill<1>, g, b, 0, s, grid, blocks, nblocks, geo); break;
-    case 2: hipLaunchKernelGGL(k_openfill<2>, g, b, 0, s, grid, blocks, nblocks, geo); break;
-    default: hipLaunchKernelGGL(k_openfill<3>, g, b, 0, s, grid, blocks, nblocks, geo); break;
+    case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
+    case 1: hipLaunchKernelGGL(k_openfill<1>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
+    case 2: hipLaunchKernelGGL(k_openfill<2>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
+    default: hipLaunchKernelGGL(k_openfill<3>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
   }
 }
 

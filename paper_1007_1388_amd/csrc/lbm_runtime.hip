@@ -31,7 +31,8 @@ void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev*
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
                    const Phys<float>& pf, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
-void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo, hipStream_t s);
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo,
+                     const double* side, hipStream_t s);
 void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const double* rho, const double* u,
                     long long N, hipStream_t s);
 void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, const double hg[3], double* rho,
@@ -117,6 +118,7 @@ struct lbm_ctx {
   double* d_partial = nullptr;
   int nparts = 1024;
   double* d_red = nullptr;
+  double* d_side = nullptr;  // open x faces: [face][nz][ny][16] (see SweepArgs::side)
   void* d_stage = nullptr;
   double* d_umark = nullptr;   // [rho | u_x | u_y | u_z] snapshot, FP64, 4 N
   long long mark_steps = -1;   // step count of the snapshot, -1 = none
@@ -346,6 +348,7 @@ SweepArgs sweep_args(const lbm_ctx* c, int from) {
   a.items = c->d_items;
   a.mask = c->d_mask;
   a.ghost = c->d_ghost;
+  a.side = c->d_side;
   a.nitems = (int)c->items_h.size();
   a.geo = c->geo;
   return a;
@@ -394,10 +397,13 @@ void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
 // Cells per lane the sweep of schedule s runs with (0 = automatic = one: with
 // a single cell per lane the sweep keeps more waves resident and measured
 // faster for every storage mode on gfx950).
-int cells_per_lane(const lbm_ctx* c, const lbm_schedule& s) {
-  const bool two_ok = c->x_even && sweep_vec2_ok(c->prec, c->f64math);
-  return s.cells_per_lane == 2 && two_ok ? 2 : 1;
+// Two cells per lane: F16S/BF16S or F32 with FP64 math, even x extents, and
+// no open faces (the sweep keeps one face cell per lane for them).
+bool vec2_allowed(const lbm_ctx* c) {
+  return c->x_even && sweep_vec2_ok(c->prec, c->f64math) && !c->geo.open[0] && !c->geo.open[1];
 }
+
+int cells_per_lane(const lbm_ctx* c, const lbm_schedule& s) { return s.cells_per_lane == 2 && vec2_allowed(c) ? 2 : 1; }
 
 void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   const SweepArgs a = sweep_args(c, from);
@@ -415,7 +421,7 @@ bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
 // and the boundary nodes of open faces.
 void enqueue_post(lbm_ctx* c, int g, hipStream_t s) {
   if (c->sched.fused_exchange != 1) enqueue_exchange(c, g, s, c->sched.fused_exchange == 2);
-  if (has_open(c)) launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->geo, s);
+  if (has_open(c)) launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->geo, c->d_side, s);
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
@@ -629,6 +635,7 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   if (!build_tiling(p->dims, blocks, nblocks, cuts, owner, err)) return fail(LBM_EINVAL, err);
   if (any_open && (cuts[1].size() != 2 || cuts[2].size() != 2))
     return fail(LBM_EINVAL, "open x faces need one Block across y and across z");
+  if (any_open && p->dims[0] < 2) return fail(LBM_EINVAL, "open x faces need nx >= 2");
 
   lbm_ctx* c = new lbm_ctx();
   c->p = *p;
@@ -838,8 +845,10 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->d_rim = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->rim_h.size()));
   c->d_partial = (double*)dalloc(c, sizeof(double) * 6 * c->nparts);
   c->d_red = (double*)dalloc(c, sizeof(double) * 8);
+  if (c->geo.open[0] || c->geo.open[1])
+    c->d_side = (double*)dalloc(c, sizeof(double) * 32 * (size_t)p->dims[1] * p->dims[2]);
   if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_rim ||
-      !c->d_partial || !c->d_red)
+      !c->d_partial || !c->d_red || ((c->geo.open[0] || c->geo.open[1]) && !c->d_side))
     return bail(LBM_ENOMEM, "device allocation failed");
   if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1090,8 +1099,9 @@ lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s) {
   if (!c || !s) return fail(LBM_EINVAL, "NULL argument");
   std::string err;
   if (!sched_valid(*s, err)) return fail(LBM_EINVAL, err);
-  if (s->cells_per_lane == 2 && !(c->x_even && sweep_vec2_ok(c->prec, c->f64math)))
-    return fail(LBM_EINVAL, "two cells per lane need F16S/BF16S (or F32 with FP64 math) and even x extents");
+  if (s->cells_per_lane == 2 && !vec2_allowed(c))
+    return fail(LBM_EINVAL,
+                "two cells per lane need F16S/BF16S (or F32 with FP64 math), even x extents and no open faces");
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   const lbm_schedule old = c->sched;
@@ -1207,7 +1217,7 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
         if (knob == 3) s.nontemporal = (int)q;
         if (knob == 4) s.fused_exchange = (int)q;
         if (knob == 5) {
-          if (!(c->x_even && sweep_vec2_ok(c->prec, c->f64math))) continue;
+          if (!vec2_allowed(c)) continue;
           s.cells_per_lane = (int)q + 1;
         }
         cand.push_back(s);

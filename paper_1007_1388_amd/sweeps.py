@@ -2,6 +2,7 @@
 
   python -m paper_1007_1388_amd.sweeps size   [--steps 200]   # single-Block periodic cubes
   python -m paper_1007_1388_amd.sweeps blocks [--steps 200]   # 384^3 split into 1..216 Blocks, porous
+  python -m paper_1007_1388_amd.sweeps open   [--steps 200]   # open x faces against periodic x
 
 size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
         storage, started from rest with g_x = 1e-6, tau 0.8: MLUPS against N,
@@ -13,6 +14,11 @@ blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
         sweep, 1 fully fused), for the porous channel in its uneven Blocks and
         for 64 uneven Blocks (4x4x4, edges from {32, 48, 64}): the cost of
         Blocks and of their on-GPU copies, Sec. 5.2.
+open:   a 512x256x256 duct (y periodic, z walls), FP32: x periodic with a
+        body force against a velocity inlet and a pressure outlet on the x
+        faces, as one Block and as 4 Blocks along x; the second column of
+        times is then the post-sweep work (exchange and the boundary nodes of
+        the open faces).
 
 Prints one JSON line per case.
 """
@@ -31,9 +37,10 @@ HBM_PEAK_GBS = 8000.0
 
 
 def measure(dims, precision, steps, blocks=None, solid=None, walls=(False, False, False), tau=0.8,
-            force=(1e-6, 0.0, 0.0), fused=0, graph_steps=10):
+            force=(1e-6, 0.0, 0.0), fused=0, graph_steps=10, open_x=None):
     import torch
-    lat = lbm.Lattice(dims, blocks=blocks, walls=walls, tau=tau, force=force, precision=precision)
+    lat = lbm.Lattice(dims, blocks=blocks, walls=walls, tau=tau, force=force, precision=precision,
+                      open_x=open_x)
     if solid is not None:
         lat.set_geometry(solid)
     lat.set_schedule(fused_exchange=fused, graph_steps=graph_steps)
@@ -92,9 +99,22 @@ def block_sweep(steps):
                               split="4x4x4 uneven {32,48,64}", precision="f32", fused=fused, **r)), flush=True)
 
 
+def open_sweep(steps):
+    dims = (512, 256, 256)
+    opn = {"-x": ("velocity", (0.02, 0.0, 0.0)), "+x": ("pressure", 1.0)}
+    for label, walls, force, ox in (("x periodic, g_x = 1e-6", (False, False, True), (1e-6, 0, 0), None),
+                                    ("x velocity inlet / pressure outlet", (True, False, True), (0, 0, 0), opn)):
+        for nb in (1, 4):
+            blocks = inputs.uniform_blocks(dims, (nb, 1, 1))
+            for fused in ((0,) if nb == 1 else (0, 2)):
+                r = measure(dims, "f32", steps, blocks=blocks, walls=walls, force=force, fused=fused, open_x=ox)
+                print(json.dumps(dict(study="open", domain="512x256x256 duct", x=label, split="%dx1x1" % nb,
+                                      precision="f32", fused=fused, **r)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["size", "blocks"])
+    ap.add_argument("study", choices=["size", "blocks", "open"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--sizes", default="64-512:32")
     args = ap.parse_args()
@@ -104,6 +124,8 @@ def main():
         lo, rest = args.sizes.split("-")
         hi, st = rest.split(":")
         size_sweep(args.steps, range(int(lo), int(hi) + 1, int(st)))
+    elif args.study == "open":
+        open_sweep(args.steps)
     else:
         block_sweep(args.steps)
 

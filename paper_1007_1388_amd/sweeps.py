@@ -3,6 +3,7 @@
   python -m paper_1007_1388_amd.sweeps size   [--steps 200]   # single-Block periodic cubes
   python -m paper_1007_1388_amd.sweeps blocks [--steps 200]   # 384^3 split into 1..216 Blocks, porous
   python -m paper_1007_1388_amd.sweeps open   [--steps 200]   # open x faces against periodic x
+  python -m paper_1007_1388_amd.sweeps pad    [--steps 200]   # odd Block sizes and row padding
 
 size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
         storage, started from rest with g_x = 1e-6, tau 0.8: MLUPS against N,
@@ -14,6 +15,11 @@ blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
         sweep, 1 fully fused), for the porous channel in its uneven Blocks and
         for 64 uneven Blocks (4x4x4, edges from {32, 48, 64}): the cost of
         Blocks and of their on-GPU copies, Sec. 5.2.
+pad:    single-Block periodic cubes of odd and even edge around 64, 70,
+        128 and 256 (the paper's odd-size effects, Sec. 5.1) with rows
+        aligned to 128-byte lines and no extra padding (row_pad -1) or one
+        or two extra lines per row, with streaming stores, and without
+        padding with ordinary stores, FP32 and FP64: MLUPS against the edge.
 open:   a 512x256x256 duct (y periodic, z walls), FP32: x periodic with a
         body force against a velocity inlet and a pressure outlet on the x
         faces, as one Block and as 4 Blocks along x; the second column of
@@ -37,13 +43,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def measure(dims, precision, steps, blocks=None, solid=None, walls=(False, False, False), tau=0.8,
-            force=(1e-6, 0.0, 0.0), fused=0, graph_steps=10, open_x=None):
+            force=(1e-6, 0.0, 0.0), fused=0, graph_steps=10, open_x=None, row_pad=0, nontemporal=1):
     import torch
     lat = lbm.Lattice(dims, blocks=blocks, walls=walls, tau=tau, force=force, precision=precision,
-                      open_x=open_x)
+                      open_x=open_x, row_pad=row_pad)
     if solid is not None:
         lat.set_geometry(solid)
-    lat.set_schedule(fused_exchange=fused, graph_steps=graph_steps)
+    lat.set_schedule(fused_exchange=fused, graph_steps=graph_steps, nontemporal=nontemporal)
     lat.step(20)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -99,6 +105,15 @@ def block_sweep(steps):
                               split="4x4x4 uneven {32,48,64}", precision="f32", fused=fused, **r)), flush=True)
 
 
+def pad_sweep(steps):
+    for n in (63, 64, 65, 69, 70, 71, 72, 127, 128, 129, 255, 256, 257):
+        for prec in ("f32", "f64"):
+            for rp, nt in ((-1, 1), (1, 1), (2, 1), (-1, 0)):
+                r = measure((n, n, n), prec, steps, row_pad=rp, nontemporal=nt)
+                print(json.dumps(dict(study="pad", n=n, precision=prec, row_pad=rp, nontemporal=nt, **r)),
+                      flush=True)
+
+
 def open_sweep(steps):
     dims = (512, 256, 256)
     opn = {"-x": ("velocity", (0.02, 0.0, 0.0)), "+x": ("pressure", 1.0)}
@@ -114,7 +129,7 @@ def open_sweep(steps):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["size", "blocks", "open"])
+    ap.add_argument("study", choices=["size", "blocks", "open", "pad"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--sizes", default="64-512:32")
     args = ap.parse_args()
@@ -126,6 +141,8 @@ def main():
         size_sweep(args.steps, range(int(lo), int(hi) + 1, int(st)))
     elif args.study == "open":
         open_sweep(args.steps)
+    elif args.study == "pad":
+        pad_sweep(args.steps)
     else:
         block_sweep(args.steps)
 

@@ -243,6 +243,19 @@ const char* lbm_last_error(void);
 lbm_status lbm_bw_probe(void* dst, const void* src, size_t bytes, int32_t reps, void* stream,
                         double* ms_per_copy);
 
+/* HBM bandwidth ceilings of plain access patterns (the patterns the sweep's
+ * bandwidth is read against; Sec. 3.1's attainable-bandwidth benchmark for
+ * three patterns): kind 0 reads `a`, 1 writes `b`, 2 copies a -> b, over
+ * `bytes` (a multiple of 16, device buffers of that size; b is overwritten,
+ * a is only read) in 16-byte accesses, `unroll` (1, 2, 4 or 8) independent
+ * accesses in flight per thread, nontemporal = 1 for streaming loads and
+ * stores, `grid` workgroups of 256 threads (0: 16 per compute unit).  After
+ * one warm-up pass, reps passes on `stream`; *ms = mean time per pass.
+ * LBM_EINVAL on bad arguments (a may be NULL for kind 1), LBM_EDEVICE on a
+ * HIP error.  Synchronises. */
+lbm_status lbm_hbm_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void* a, void* b,
+                         size_t bytes, int32_t grid, int32_t reps, void* stream, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "conv3d.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "conv3d.hip", "hbm_probe.hip"]
 
 # Packed FP32 instructions are kept off: the code is plain scalar float/double.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -77,7 +77,7 @@ SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_
            "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
            "lbm_sums", "lbm_get_state", "lbm_set_state",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_autotune", "lbm_info_get", "lbm_destroy",
-           "lbm_strerror", "lbm_last_error", "lbm_bw_probe"]
+           "lbm_strerror", "lbm_last_error", "lbm_bw_probe", "lbm_hbm_probe"]
 
 _lib = None
 
@@ -117,6 +117,8 @@ def load(path=LIB_PATH):
         "lbm_info_get": [P, ctypes.POINTER(lbm_info)],
         "lbm_destroy": [P],
         "lbm_bw_probe": [P, P, ctypes.c_size_t, ctypes.c_int32, P, dp],
+        "lbm_hbm_probe": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_size_t, ctypes.c_int32,
+                          ctypes.c_int32, P, dp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -251,6 +253,15 @@ def lbm_bw_probe(dst_ptr, src_ptr, nbytes, reps, stream):
     ms = ctypes.c_double()
     _check(load().lbm_bw_probe(dst_ptr, src_ptr, int(nbytes), int(reps), stream, ctypes.byref(ms)),
            "lbm_bw_probe")
+    return ms.value
+
+
+def lbm_hbm_probe(kind, unroll, nontemporal, a_ptr, b_ptr, nbytes, grid, reps, stream):
+    """Mean milliseconds per pass of an HBM access pattern (0 read, 1 write,
+    2 copy); see lbm.h."""
+    ms = ctypes.c_double()
+    _check(load().lbm_hbm_probe(int(kind), int(unroll), int(nontemporal), a_ptr, b_ptr, int(nbytes), int(grid),
+                                int(reps), stream, ctypes.byref(ms)), "lbm_hbm_probe")
     return ms.value
 
 

@@ -4,6 +4,7 @@
   python -m paper_1007_1388_amd.sweeps blocks [--steps 200]   # 384^3 split into 1..216 Blocks, porous
   python -m paper_1007_1388_amd.sweeps open   [--steps 200]   # open x faces against periodic x
   python -m paper_1007_1388_amd.sweeps pad    [--steps 200]   # odd Block sizes and row padding
+  python -m paper_1007_1388_amd.sweeps hbm                    # HBM ceilings of read, write, copy
 
 size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
         storage, started from rest with g_x = 1e-6, tau 0.8: MLUPS against N,
@@ -20,6 +21,11 @@ pad:    single-Block periodic cubes of odd and even edge around 64, 70,
         aligned to 128-byte lines and no extra padding (row_pad -1) or one
         or two extra lines per row, with streaming stores, and without
         padding with ordinary stores, FP32 and FP64: MLUPS against the edge.
+hbm:    read-only, write-only and copy streams over 2 GiB buffers (well past
+        the 256 MB Infinity Cache) with 1-8 accesses in flight per thread,
+        streaming or ordinary, several grid sizes: the attainable bandwidth
+        of each pattern (lbm_hbm_probe), against which the sweep (one read
+        and one write of every value, the copy pattern) is read.
 open:   a 512x256x256 duct (y periodic, z walls), FP32: x periodic with a
         body force against a velocity inlet and a pressure outlet on the x
         faces, as one Block and as 4 Blocks along x; the second column of
@@ -114,6 +120,23 @@ def pad_sweep(steps):
                       flush=True)
 
 
+def hbm_sweep(reps=10):
+    import torch
+    nbytes = 2 << 30
+    a = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    for kind, name, moved in ((0, "read", 1), (1, "write", 1), (2, "copy", 2)):
+        for unroll in (1, 2, 4, 8):
+            for nt in (1, 0):
+                for grid in (1024, 4096, 16384, 65536):
+                    ms = lbm.lbm_hbm_probe(kind, unroll, nt, a.data_ptr(), b.data_ptr(), nbytes, grid, reps, st)
+                    gbs = moved * nbytes / (ms * 1e-3) / 1e9
+                    print(json.dumps(dict(study="hbm", pattern=name, unroll=unroll, nontemporal=nt, grid=grid,
+                                          ms=round(ms, 5), gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))),
+                          flush=True)
+
+
 def open_sweep(steps):
     dims = (512, 256, 256)
     opn = {"-x": ("velocity", (0.02, 0.0, 0.0)), "+x": ("pressure", 1.0)}
@@ -129,7 +152,7 @@ def open_sweep(steps):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["size", "blocks", "open", "pad"])
+    ap.add_argument("study", choices=["size", "blocks", "open", "pad", "hbm"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--sizes", default="64-512:32")
     args = ap.parse_args()
@@ -143,6 +166,8 @@ def main():
         open_sweep(args.steps)
     elif args.study == "pad":
         pad_sweep(args.steps)
+    elif args.study == "hbm":
+        hbm_sweep()
     else:
         block_sweep(args.steps)
 

@@ -125,3 +125,7 @@ def test_null_arguments_rejected():
     assert lib.lbm_residual_since_mark(None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
     assert lib.lbm_bw_probe(None, None, 16, 1, None, None) == lbm.LBM_EINVAL
+    for bad in [(3, 1, 1, None, 1, 16, 0, 1, None), (0, 3, 1, 1, 1, 16, 0, 1, None), (0, 1, 1, None, 1, 16, 0, 1, None),
+                (2, 1, 1, 1, 1, 24, 0, 1, None), (1, 1, 1, None, 1, 16, 0, 0, None)]:
+        ms = ctypes.c_double()
+        assert lib.lbm_hbm_probe(*bad[:8], bad[8], ctypes.byref(ms)) == lbm.LBM_EINVAL

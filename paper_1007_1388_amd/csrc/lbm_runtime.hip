@@ -805,15 +805,18 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
 
   // Axes on which a Block is its own neighbour across both faces: the sweep
   // reads across them from the Block itself (no ghost values, no copies).
-  // y only where every wave holds one row of the Block (x extent > 64 also
-  // with two cells per lane), so that the wrap is uniform per wave.
+  // y only where every wave holds one row of the Block, so that the wrap is
+  // uniform per wave: x extent > 64 (also with two cells per lane), or 64
+  // where the storage mode never runs two cells per lane.
+  const bool vec2_possible = sweep_vec2_ok(c->prec, c->f64math);
   for (int j = 0; j < nblocks; ++j) {
     BlockDev& B = c->bh[j];
     B.wrap = 0;
     const int st[3] = {1, 3, 9};
     for (int k = 0; k < 3; ++k) {
       const bool self = c->nbh[(size_t)j * 27 + 13 - st[k]].id == j && c->nbh[(size_t)j * 27 + 13 + st[k]].id == j;
-      if (self && (k != 1 || B.dim[0] > 64)) B.wrap |= 1 << k;
+      const bool one_row = B.dim[0] > 64 || (B.dim[0] == 64 && !vec2_possible);
+      if (self && (k != 1 || one_row)) B.wrap |= 1 << k;
     }
   }
 

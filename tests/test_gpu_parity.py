@@ -190,6 +190,24 @@ def test_self_wrapping_block_matches_tiling(precision):
         lat.close()
 
 
+@pytest.mark.parametrize("precision,f64m", [("f32", False), ("f64", False), ("f32", True), ("f16s", False)])
+def test_rows_of_64_cells_bitwise_across_tilings(precision, f64m):
+    """One Block with rows of exactly 64 cells wraps onto itself in y when the
+    sweep runs one cell per lane (FP32 mixed, FP64), and takes the exchange
+    where two cells per lane are possible (FP32 with FP64 math, 16-bit): every
+    case equals a tiling that exchanges, bit for bit, with two cells per lane
+    as well where allowed."""
+    dims = (64, 12, 9)
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 3), seed=9)
+    case = channel(dims=dims, solid=solid, force=(1e-5, 3e-6, 0.0), tau=0.75, seed=4)
+    ref = run_gpu(case, 17, blocks=inputs.uniform_blocks(dims, (2, 2, 1)), precision=precision, fp64_math=f64m)
+    scheds = [None] + ([dict(cells_per_lane=2)] if precision == "f16s" or f64m else [])
+    for sched in scheds:
+        lat = run_gpu(case, 17, precision=precision, fp64_math=f64m, schedule=sched)
+        assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+        lat.close()
+
+
 def test_self_wrapping_periodic_box_matches_oracle():
     """Fully periodic box as one Block (wraps on all three axes) against the
     oracle, and against a two-Block tiling bit for bit."""

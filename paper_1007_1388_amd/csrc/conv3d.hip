@@ -480,6 +480,167 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const uint16_t* __restrict__
     }
 }
 
+// ------------------------------------ fwd / bwd-data, stride 1, 3x3x3 halos
+// The stride-1 3x3x3 products with 32 or 64 output columns (the
+// full-resolution layers), where every gathered A element feeds only two or
+// four MFMAs and the tap-major kernel runs at the L1/L2 gather rate.  A
+// workgroup owns an 8 x 32 block of output voxels (rows h0.., columns w0..
+// of one plane) and all output columns; per kernel plane kd and 32-channel
+// chunk it stages in LDS
+//   * the input halo  [10 rows][34 columns][32 channels] of source plane
+//     d + kd - 1 (forward) or d + 1 - kd (input gradient), and
+//   * the weights     [9 taps][columns][32 channels] of that plane and chunk,
+// then runs the nine (kh, kw) taps on them: both MFMA operands are 16-byte
+// LDS reads with channels as K, so each input value is fetched from memory
+// once per (kd, chunk) instead of nine times.  The next stage's loads go to
+// registers while the taps run and reach LDS after the next barrier.  Wave v owns output rows
+// h0 + 2v and h0 + 2v + 1 (four 16-voxel fragments).  MODE 1 reads the taps
+// mirrored (source i + 1 - k) with the transposed weights.
+template <int MODE, int FN>
+__global__ void __launch_bounds__(256) k_conv_halo(DArgs a) {
+  constexpr int BN = 16 * FN;
+  constexpr int HR = 10, HC = 34, PC = 40;  // halo rows, columns, cell pitch (bf16)
+  constexpr int PW = 40;                    // weight row pitch (bf16)
+  constexpr int NX = HR * HC * 4;           // halo chunks of 8 channels
+  constexpr int NW = 9 * BN * 4;            // weight chunks
+  constexpr unsigned OOB = 0x80000000u;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[HR * HC * PC];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[9 * BN * PW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Geo gs = a.gs, go = a.go;
+  // output block of this workgroup
+  const int nwb = go.w / 32, nhb = (go.h + 7) / 8;
+  int bx = blockIdx.x;
+  const int wb = bx % nwb;
+  bx /= nwb;
+  const int hb = bx % nhb;
+  bx /= nhb;
+  const int d = bx % go.d, n = bx / go.d;
+  const int h0 = hb * 8, w0 = wb * 32;
+  const int C = a.C;
+  const int ncols = go.c;
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(a.src, a.src_bytes);
+  const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.wk, a.wk_bytes);
+
+  f32x4 acc[4][FN];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // Per-thread staging slots.  Halo slot i covers cell (r, c) and 8
+  // channels q; its offset within the source plane is fixed, the plane and
+  // the chunk change per stage.  Weight slot j covers one column's 8
+  // channels of one (kh, kw) tap.  A slot outside the tensor takes the
+  // offset 2^30 elements, which lands past the buffer's range (real offsets
+  // stay below 2^30 elements); a plane outside is sent there by the high bit.
+  constexpr int SX = (NX + 255) / 256, SW = (NW + 255) / 256;
+  constexpr int FAR = 1 << 30;
+  int xoff[SX];
+#pragma unroll
+  for (int i = 0; i < SX; ++i) {
+    const int id = tid + i * 256;
+    const int cell = id >> 2, q = id & 3;
+    const int r = cell / HC, c = cell - r * HC;
+    const int hs = h0 - 1 + r, ws = w0 - 1 + c;
+    const bool ok = id < NX && hs >= 0 && hs < gs.h && ws >= 0 && ws < gs.w;
+    xoff[i] = ok ? (hs * gs.w + ws) * gs.ldc + q * 8 : FAR;
+  }
+  int woff[SW];
+#pragma unroll
+  for (int j = 0; j < SW; ++j) {
+    const int id = tid + j * 256;
+    const int t9 = id / (BN * 4), rem = id - t9 * (BN * 4);
+    const int col = rem >> 2, q = rem & 3;
+    woff[j] = id < NW && col < ncols ? col * a.kstride + t9 * C + q * 8 : FAR;
+  }
+  const int plane = gs.h * gs.w * gs.ldc;
+  u32x4 xr[SX], wr[SW];
+  // issue the loads of stage st = kd * (C / 32) + chunk into registers
+  auto fetch = [&](int st) {
+    const int cpk = C >> 5;
+    const int kd = st / cpk, c0 = (st - kd * cpk) * 32;
+    const int ds = MODE == 0 ? d + kd - 1 : d + 1 - kd;
+    const unsigned dpen = ds >= 0 && ds < gs.d ? 0u : OOB;
+    const int pb = (n * gs.d + ds) * plane + c0;
+#pragma unroll
+    for (int i = 0; i < SX; ++i)
+      xr[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, (unsigned)(pb + xoff[i]) * 2u | dpen, 0, 0);
+    const int wb_ = kd * 9 * C + c0;
+#pragma unroll
+    for (int j = 0; j < SW; ++j)
+      wr[j] = __builtin_amdgcn_raw_buffer_load_b128(rw, (unsigned)(woff[j] + wb_) * 2u, 0, 0);
+  };
+  // LDS homes of the slots
+  auto xdst = [&](int i) {
+    const int id = tid + i * 256;
+    return (id >> 2) * PC + (id & 3) * 8;
+  };
+  auto wdst = [&](int j) {
+    const int id = tid + j * 256;
+    const int t9 = id / (BN * 4), rem = id - t9 * (BN * 4);
+    return (t9 * BN + (rem >> 2)) * PW + (rem & 3) * 8;
+  };
+
+  const int L = lane & 15, g = lane >> 4;
+  const int nst = 3 * (C >> 5);
+  fetch(0);
+  for (int st = 0; st < nst; ++st) {
+    __syncthreads();  // the previous stage's readers are done
+#pragma unroll
+    for (int i = 0; i < SX; ++i)
+      if (tid + i * 256 < NX) *(u32x4*)(&Xs[xdst(i)]) = xr[i];
+#pragma unroll
+    for (int j = 0; j < SW; ++j)
+      if (tid + j * 256 < NW) *(u32x4*)(&Ws[wdst(j)]) = wr[j];
+    __syncthreads();
+    if (st + 1 < nst) fetch(st + 1);  // in flight while the taps run
+#pragma unroll
+    for (int kh = 0; kh < 3; ++kh)
+#pragma unroll
+      for (int kw = 0; kw < 3; ++kw) {
+        // source offset of the tap in the halo: forward + (kh, kw),
+        // input gradient + (2 - kh, 2 - kw)
+        const int oh = MODE == 0 ? kh : 2 - kh, ow = MODE == 0 ? kw : 2 - kw;
+        bf16x8 af[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int r = 2 * wave + (f >> 1), c = (f & 1) * 16 + L;
+          af[f] = *(const bf16x8*)(&Xs[((r + oh) * HC + c + ow) * PC + g * 8]);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const bf16x8 bfr = *(const bf16x8*)(&Ws[((kh * 3 + kw) * BN + j * 16 + L) * PW + g * 8]);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[f], bfr, acc[f][j], 0, 0, 0);
+        }
+      }
+  }
+  // epilogue: lane holds D[(lane/16)*4 + q][lane%16] of each tile
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int h = h0 + 2 * wave + (f >> 1);
+    if (h >= go.h) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = w0 + (f & 1) * 16 + g * 4 + q;
+      const long long vo = (((long long)n * go.d + d) * go.h + h) * go.w + w;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = j * 16 + L;
+        if (col >= ncols) continue;
+        float v = acc[f][j][q];
+        if (a.bias) v += a.bias[col];
+        if (a.relu) v = v > 0.f ? v : 0.f;
+        const long long o = vo * go.ldc + col;
+        if (a.act && !(bf2f(a.act[vo * a.act_ldc + col]) > 0.f)) v = 0.f;
+        if (a.accumulate) v += bf2f(a.out[o]);
+        a.out[o] = f2bf(v);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------- bwd-weight, 3x3x3 halos
 // dw[co][tap*Cin + ci] += sum_v dy[v][co] * x[src(v, tap)][ci] for 3x3x3
 // kernels with Cin a multiple of 32.  A workgroup owns one kernel plane kd,
@@ -885,6 +1046,21 @@ void launch_tap_cols(const DArgs& a, long long rows, int nz, hipStream_t s) {
     launch_tap<MODE, CLS, 2, 8>(a, rows, nz, s);
 }
 
+// the halo kernel: stride-1 3x3x3 products onto whole 32-column row pieces
+// with at most 64 output columns
+bool halo_fits(const lbm_tensor5* src, const lbm_tensor5* out, int ksize, int stride) {
+  return ksize == 3 && stride == 1 && src->c % 32 == 0 && out->w % 32 == 0 && out->c <= 64;
+}
+
+template <int MODE>
+void launch_halo(const DArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)((a.go.w / 32) * ((a.go.h + 7) / 8) * a.go.d * a.go.n);
+  if (a.go.c <= 32)
+    hipLaunchKernelGGL((k_conv_halo<MODE, 2>), dim3(g), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_conv_halo<MODE, 4>), dim3(g), dim3(256), 0, s, a);
+}
+
 int grid1(long long n) {
   long long g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -914,7 +1090,10 @@ lbm_status lbm_conv3d_fwd(const lbm_tensor5* x, const uint16_t* w, const float* 
     const DArgs a{(const uint16_t*)x->ptr, gs, (unsigned)view_bytes(x), w, kpad,
                   (unsigned)((long long)y->c * kpad * 2), bias, (uint16_t*)y->ptr, go, nullptr, 0, ksize, stride,
                   relu, 0, x->c};
-    launch_tap_cols<0, false>(a, M, 1, s);
+    if (halo_fits(x, y, ksize, stride))
+      launch_halo<0>(a, s);
+    else
+      launch_tap_cols<0, false>(a, M, 1, s);
   } else if (y->c <= 16) {
     dim3 g((unsigned)((M + BM - 1) / BM), (y->c + 15) / 16);
     hipLaunchKernelGGL((k_conv_gemm<0, 16>), g, b, 0, s, (const uint16_t*)x->ptr, gs, w, kpad, bias,
@@ -959,6 +1138,8 @@ lbm_status lbm_conv3d_bwd_data(const lbm_tensor5* dy, const uint16_t* w_t, const
       // rows of the largest parity class; smaller classes mask their tail
       const long long rows = (long long)dx->n * ((dx->d + 1) / 2) * ((dx->h + 1) / 2) * ((dx->w + 1) / 2);
       launch_tap_cols<1, true>(a, rows, 8, s);
+    } else if (halo_fits(dy, dx, ksize, stride)) {
+      launch_halo<1>(a, s);
     } else {
       launch_tap_cols<1, false>(a, M, 1, s);
     }

@@ -48,6 +48,14 @@ CASES = [
     dict(n=1, d=6, h=7, w=16, ci=64, co=48, k=3, s=2),
     dict(n=1, d=4, h=5, w=2, ci=32, co=32, k=3, s=1),
     dict(n=1, d=3, h=3, w=70, ci=32, co=32, k=3, s=2),
+    # stride-1 3x3x3 onto rows of whole 32-voxel pieces with at most 64
+    # output columns: the halo-staged forward and input gradient, 32 and 64
+    # columns (a partial one of 48), one to three 32-channel chunks, a
+    # partial 8-row block, two pieces per row
+    dict(n=2, d=5, h=11, w=32, ci=32, co=32, k=3, s=1),
+    dict(n=1, d=3, h=8, w=64, ci=64, co=32, k=3, s=1),
+    dict(n=1, d=4, h=7, w=32, ci=64, co=64, k=3, s=1),
+    dict(n=1, d=4, h=5, w=32, ci=96, co=48, k=3, s=1),
 ]
 
 

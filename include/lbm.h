@@ -228,6 +228,49 @@ lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s);
 lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
                         lbm_schedule* chosen);
 
+/* Heterogeneous runs (Sec. 4.5, Sec. 5.3): the Blocks in ids[0..n) run on
+ * the host CPU, the rest on the GPU.  Each Block carries the hardware it runs
+ * on; a host Block keeps both grids in pinned host memory (hipHostMalloc)
+ * with the same layout as on the GPU, and `threads` host threads (0: up to
+ * 16) sweep them while the GPU sweeps its Blocks.  Values that cross between
+ * a host and a GPU Block each step go through exchange buffers of one format
+ * that both sides pack and unpack; the ghost exchange among GPU Blocks runs
+ * in the copy kernel (fused_exchange is not used) and steps are launched
+ * one by one (graph_steps is not used).  The host sweep repeats the GPU
+ * arithmetic operation for operation, so results equal the all-GPU run bit
+ * for bit.  n = 0 returns every Block to the GPU.  The state is carried
+ * over; lbm_macroscopic, lbm_residual*, lbm_sums and lbm_get_state copy the
+ * host Blocks' state to the device first.  Synchronises.
+ * LBM_EINVAL: n < 0 or > the Block count, ids NULL with n > 0, an id out of
+ * range or repeated, threads outside [0, 1024], F16S/BF16S storage, or open
+ * faces (with n > 0); LBM_ENOMEM: host or device allocation failed (every
+ * Block then stays on the GPU).  lbm_autotune refuses a context with host
+ * Blocks. */
+lbm_status lbm_set_host_blocks(lbm_ctx* c, const int32_t* ids, int32_t n, int32_t threads);
+
+/* n steps (1 <= n <= 100000) of a context with host Blocks, with the mean
+ * per step of: the GPU sweep (HIP events), the host sweep (wall clock, from
+ * the GPU launch to the last host thread), the exchange phase (wall clock,
+ * from the end of both sweeps) and the whole step (wall clock), in
+ * milliseconds.  LBM_ESTATE without host Blocks.  Synchronises. */
+lbm_status lbm_step_host_timed(lbm_ctx* c, int64_t n, double* gpu_sweep_ms, double* cpu_sweep_ms,
+                               double* exchange_ms, double* step_ms);
+
+/* Static load balance (Sec. 5.3: Blocks per process raised until the work
+ * is balanced): times trial_steps steps with every Block on the GPU, then
+ * the host sweep of the last Block of the list, and puts the last k Blocks
+ * of the list on the host, k the largest for which the host's predicted
+ * sweep time (fluid cells over its measured rate) stays within the GPU's;
+ * if the measured step with that split is not faster than the GPU alone, k
+ * is 0.  The split is applied (lbm_set_host_blocks with `threads`) and
+ * *n_host = k; ms_gpu_only / ms_balanced (may be NULL) receive the measured
+ * step times of the GPU alone and of the split tried (with k = 0: of one
+ * host Block).  The state is saved before and restored after the trials.
+ * LBM_EINVAL: NULL c or n_host, trial_steps outside [1, 10000], threads
+ * outside [0, 1024], F16S/BF16S storage or open faces. */
+lbm_status lbm_balance_host_blocks(lbm_ctx* c, int32_t threads, int32_t trial_steps, int32_t* n_host,
+                                   double* ms_gpu_only, double* ms_balanced);
+
 /* Static facts and counters of a context.  Synchronises. */
 lbm_status lbm_info_get(lbm_ctx* c, lbm_info* info);
 

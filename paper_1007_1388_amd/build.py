@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "conv3d.hip", "hbm_probe.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "conv3d.hip", "hbm_probe.hip", "lbm_host.cpp"]
 
 # Packed FP32 instructions are kept off: the code is plain scalar float/double.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -17,7 +17,10 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-munsafe-fp-atomics", "-Wno-unused-result"]
 # per-source extras: the convolution kernels keep MFMA accumulators in
 # VGPRs, which spares the AGPR copies the K loop otherwise carries
-EXTRA = {"conv3d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"conv3d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         # the host sweep of heterogeneous runs: x86-64 FMA for the fused
+         # multiply-adds the GPU arithmetic prescribes
+         "lbm_host.cpp": ["-mavx2", "-mfma", "-pthread"]}
 
 
 def hipcc():
@@ -32,7 +35,7 @@ def build(verbose=False, jobs=3):
     objs, procs = [], []
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     for s in srcs:
-        obj = os.path.join(CSRC, "_" + s.replace(".hip", ".o"))
+        obj = os.path.join(CSRC, "_" + os.path.splitext(s)[0] + ".o")
         cmd = [hipcc(), *HIPFLAGS, *EXTRA.get(s, []), "-c", os.path.join(CSRC, s), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -44,7 +47,7 @@ def build(verbose=False, jobs=3):
         if p.wait() != 0:
             raise RuntimeError("hipcc failed on %s" % s)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

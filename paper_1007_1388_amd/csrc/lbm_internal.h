@@ -60,10 +60,13 @@ struct ItemDev {
 // of Block `dst` in offset class d (extent ext[3] starting at lo[3], local
 // coordinates of dst, -1 or dim on the offset axes) and the ndir population
 // directions that cross into it (5 through a face, 1 through an edge), 5 bits
-// each in dirs.
+// each in dirs.  bo: where the task's values start in an exchange buffer
+// (elements; value j of cell l at bo + 5 (l - l0) + j), for tasks whose two
+// Blocks live in different memories (host-CPU Blocks).
 struct XchgTask {
   int dst, d, ndir, dirs, l0, l1;
   int lo[3], ext[3];
+  int bo, pad;
 };
 
 // Link-mask word of a cell: bit i (1..18) set when x - e_i is a solid cell
@@ -146,5 +149,30 @@ struct CellArgs {
   int has_mask;
   GridGeom geo;
 };
+
+// ---- host-CPU Blocks (heterogeneous runs, Sec. 4.5) --------------------
+// A Block on the CPU keeps its storage in host memory with the same layout
+// as on the GPU (BlockDev offsets then count from a host pool), so the
+// exchange buffers have one format for both sides.
+struct HostPool;
+HostPool* host_pool_create(int threads);
+void host_pool_destroy(HostPool* p);
+int host_pool_threads(const HostPool* p);
+
+// One sweep (pull, bounce-back, collision, stores) of the listed Blocks
+// from src to dst, rounding exactly as the GPU sweep of the same precision
+// and arithmetic mode.  blocks: host-based table; ids: the Blocks to sweep;
+// mask: host copy of the link masks (BlockDev::mask offsets into it), or
+// NULL.  ph is Phys<double> for FP64 arithmetic, Phys<float> for FP32 storage
+// with FP32 arithmetic.
+void host_sweep(HostPool* p, int prec, bool f64math, const void* src, void* dst, const BlockDev* blocks,
+                const int* ids, int nids, const uint32_t* mask, const GridGeom& geo, const Phys<double>& pd,
+                const Phys<float>& pf);
+
+// The host's share of an exchange over tasks (host-based Block table):
+// mode 0 copies neighbour values into ghost slots (both Blocks on the host),
+// 1 packs the sources into buf, 2 unpacks buf into the ghost slots.
+void host_exchange(HostPool* p, int prec, int mode, void* grid, const BlockDev* blocks, const NbrDev* nbr,
+                   const XchgTask* tasks, int ntasks, void* buf);
 
 }  // namespace lbm

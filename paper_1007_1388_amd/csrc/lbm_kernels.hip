@@ -734,10 +734,16 @@ __constant__ int kEz[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -
 // across an obstacle link (its own value replaces it), and whole lines are
 // cheaper.
 
-template <typename T>
+//
+// MODE 1 and 2 split the copy at an exchange buffer, for pairs of Blocks of
+// which one lives on the host CPU (Sec. 4.5: both sides share the buffer's
+// layout, value j of task cell l at bo + 5 (l - l0) + j): 1 packs the
+// sending Block's values into buf, 2 writes buf into the ghost slots.
+template <typename T, int MODE = 0>
 __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const BlockDev* __restrict__ blocks,
                                                   const NbrDev* __restrict__ nbr,
-                                                  const XchgTask* __restrict__ tasks, int ntasks) {
+                                                  const XchgTask* __restrict__ tasks, int ntasks,
+                                                  T* __restrict__ buf = nullptr) {
   // one workgroup per task; a thread copies every crossing direction of its
   // ghost cell, all loads before the stores
   for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
@@ -765,12 +771,17 @@ __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const Bl
         if (M.wrap & 2) py = py < 0 ? py + M.dim[1] : (py >= M.dim[1] ? py - M.dim[1] : py);
         if (M.wrap & 4) pz = pz < 0 ? pz + M.dim[2] : (pz >= M.dim[2] ? pz - M.dim[2] : pz);
         ok[j] = j < t.ndir && px >= 0 && px < M.dim[0] && py >= 0 && py < M.dim[1] && pz >= 0 && pz < M.dim[2];
-        if (ok[j]) v[j] = grid[main_off(N, i, sx, sy, sz)];
+        const long long bi = (long long)t.bo + 5ll * (L - t.l0) + j;
+        if (ok[j]) v[j] = MODE == 2 ? buf[bi] : grid[main_off(N, i, sx, sy, sz)];
       }
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
         const int i = (t.dirs >> (5 * j)) & 31;
-        if (ok[j]) grid[xplane ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz)] = v[j];
+        if (!ok[j]) continue;
+        if (MODE == 1)
+          buf[(long long)t.bo + 5ll * (L - t.l0) + j] = v[j];
+        else
+          grid[xplane ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz)] = v[j];
       }
     }
   }
@@ -1196,9 +1207,30 @@ void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev*
   if (ntasks <= 0) return;
   dim3 g(ntasks < (1 << 20) ? ntasks : (1 << 20)), b(256);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks); break;
-    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks); break;
-    default: hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks); break;
+    case 0: hipLaunchKernelGGL(k_exchange<double>, g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks, nullptr); break;
+    case 1: hipLaunchKernelGGL(k_exchange<float>, g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks, nullptr); break;
+    default:
+      hipLaunchKernelGGL(k_exchange<uint16_t>, g, b, 0, s, (uint16_t*)grid, blocks, nbr, tasks, ntasks, nullptr);
+      break;
+  }
+}
+
+// mode 1: pack the senders' values into buf; 2: unpack buf into the ghosts
+// (FP64 and FP32 storage)
+void launch_exchange_buf(int prec, int mode, void* grid, const BlockDev* blocks, const NbrDev* nbr,
+                         const XchgTask* tasks, int ntasks, void* buf, hipStream_t s) {
+  if (ntasks <= 0) return;
+  dim3 g(ntasks < (1 << 20) ? ntasks : (1 << 20)), b(256);
+  if (prec == 0) {
+    if (mode == 1)
+      hipLaunchKernelGGL((k_exchange<double, 1>), g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks, (double*)buf);
+    else
+      hipLaunchKernelGGL((k_exchange<double, 2>), g, b, 0, s, (double*)grid, blocks, nbr, tasks, ntasks, (double*)buf);
+  } else {
+    if (mode == 1)
+      hipLaunchKernelGGL((k_exchange<float, 1>), g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks, (float*)buf);
+    else
+      hipLaunchKernelGGL((k_exchange<float, 2>), g, b, 0, s, (float*)grid, blocks, nbr, tasks, ntasks, (float*)buf);
   }
 }
 

@@ -17,6 +17,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -45,6 +46,8 @@ void launch_get_state(int prec, bool f64, const void* grid, const CellArgs& a, v
 void launch_set_state(int prec, bool f64, void* grid, const CellArgs& a, const void* in, long long N,
                       hipStream_t s);
 void launch_copy16(const void* src, void* dst, long long n16, int grid, hipStream_t s);
+void launch_exchange_buf(int prec, int mode, void* grid, const BlockDev* blocks, const NbrDev* nbr,
+                         const XchgTask* tasks, int ntasks, void* buf, hipStream_t s);
 }  // namespace lbm
 
 using namespace lbm;
@@ -134,6 +137,25 @@ struct lbm_ctx {
   hipGraphExec_t g_one[2] = {nullptr, nullptr};
   hipGraphExec_t g_many[2] = {nullptr, nullptr};
   bool graphs_ok = false;
+
+  // host-CPU Blocks (heterogeneous runs, Sec. 4.5).  Their state lives in
+  // pinned host pools with the GPU layout (hbh: the Block table with host
+  // offsets); their device storage holds a copy only after host_push.
+  std::vector<char> on_host;
+  std::vector<int> host_ids;
+  HostPool* pool = nullptr;
+  void* hgrid[2] = {nullptr, nullptr};
+  std::vector<BlockDev> hbh;
+  std::vector<uint32_t> hmask;
+  std::vector<ItemDev> sweep_items_h;   // rows of the GPU Blocks
+  ItemDev* d_sweep_items = nullptr;
+  size_t sweep_items_cap = 0;
+  // exchange tasks by (sender, receiver): GPU->GPU, GPU->host, host->GPU, host->host
+  std::vector<XchgTask> t_dd, t_dh, t_hd, t_hh;
+  XchgTask *d_t_dd = nullptr, *d_t_dh = nullptr, *d_t_hd = nullptr;
+  void *d_xdn = nullptr, *d_xup = nullptr, *h_xdn = nullptr, *h_xup = nullptr;
+  size_t xdn_elems = 0, xup_elems = 0;
+  std::vector<long long> bfluid;        // fluid cells per Block
 };
 
 namespace {
@@ -174,6 +196,9 @@ void drop_graphs(lbm_ctx* c) {
   }
   c->graphs_ok = false;
 }
+
+// some Blocks run on the host CPU
+bool hetero(const lbm_ctx* c) { return !c->host_ids.empty(); }
 
 CellArgs cell_args(const lbm_ctx* c) {
   CellArgs a;
@@ -253,18 +278,29 @@ void build_items(lbm_ctx* c) {
     for (int z = 0; z < cz; ++z)
       for (int y = 0; y < b; y += rows) c->items_h.push_back({j, z, y, std::min(rows, b - y)});
   }
+  // the GPU sweep of a heterogeneous run covers the GPU Blocks only
+  c->sweep_items_h.clear();
+  if (hetero(c))
+    for (const ItemDev& it : c->items_h)
+      if (!c->on_host[it.block]) c->sweep_items_h.push_back(it);
+}
+
+lbm_status upload_list(lbm_ctx* c, const std::vector<ItemDev>& h, ItemDev** d, size_t* cap) {
+  const size_t need = std::max<size_t>(1, h.size()) * sizeof(ItemDev);
+  if (need > *cap) {
+    if (*d) dfree(c, *d);
+    *d = (ItemDev*)dalloc(c, need);
+    *cap = *d ? need : 0;
+    if (!*d) return fail(LBM_ENOMEM, "item list allocation failed");
+  }
+  if (!h.empty()) HIPCHK(hipMemcpy(*d, h.data(), h.size() * sizeof(ItemDev), hipMemcpyHostToDevice));
+  return LBM_OK;
 }
 
 lbm_status upload_items(lbm_ctx* c) {
-  const size_t need = c->items_h.size() * sizeof(ItemDev);
-  if (need > c->items_cap) {
-    if (c->d_items) dfree(c, c->d_items);
-    c->d_items = (ItemDev*)dalloc(c, need);
-    if (!c->d_items) return fail(LBM_ENOMEM, "item list allocation failed");
-    c->items_cap = need;
-  }
-  HIPCHK(hipMemcpy(c->d_items, c->items_h.data(), need, hipMemcpyHostToDevice));
-  return LBM_OK;
+  lbm_status s = upload_list(c, c->items_h, &c->d_items, &c->items_cap);
+  if (s == LBM_OK && hetero(c)) s = upload_list(c, c->sweep_items_h, &c->d_sweep_items, &c->sweep_items_cap);
+  return s;
 }
 
 // Exchange tasks: per (Block, neighbour offset) the directions that cross,
@@ -351,6 +387,10 @@ SweepArgs sweep_args(const lbm_ctx* c, int from) {
   a.side = c->d_side;
   a.nitems = (int)c->items_h.size();
   a.geo = c->geo;
+  if (hetero(c)) {
+    a.items = c->d_sweep_items;
+    a.nitems = (int)c->sweep_items_h.size();
+  }
   return a;
 }
 
@@ -407,12 +447,15 @@ int cells_per_lane(const lbm_ctx* c, const lbm_schedule& s) { return s.cells_per
 
 void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   const SweepArgs a = sweep_args(c, from);
-  const int nitems = (int)c->items_h.size();
+  const int nitems = a.nitems;
+  if (nitems < 1) return;  // every Block on the host
   int grid = nitems;
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
-  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange, c->sched.nontemporal != 0,
-               cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+  // a heterogeneous run exchanges through the copy kernel and the buffers
+  const int fx = hetero(c) ? 0 : c->sched.fused_exchange;
+  launch_sweep(c->prec, c->f64math, c->has_mask, fx, c->sched.nontemporal != 0, cells_per_lane(c, c->sched), a,
+               c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
 bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
@@ -457,8 +500,218 @@ lbm_status ensure_graphs(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// ---- host-CPU Blocks (heterogeneous runs, Sec. 4.5) ----------------------
+size_t span_elems(const BlockDev& B) { return (size_t)kQ * (size_t)B.Sf; }
+
+// Copy both grids of every host Block between its host pool slot and its
+// device storage (to_device: host -> device).
+lbm_status host_copy(lbm_ctx* c, bool to_device) {
+  for (int g = 0; g < 2; ++g)
+    for (int j : c->host_ids) {
+      const size_t bytes = span_elems(c->bh[j]) * c->sbytes;
+      char* dv = (char*)c->grid[g] + (size_t)c->bh[j].base * c->sbytes;
+      char* hv = (char*)c->hgrid[g] + (size_t)c->hbh[j].base * c->sbytes;
+      if (to_device)
+        HIPCHK(hipMemcpyAsync(dv, hv, bytes, hipMemcpyHostToDevice, c->stream));
+      else
+        HIPCHK(hipMemcpyAsync(hv, dv, bytes, hipMemcpyDeviceToHost, c->stream));
+    }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+// Before a kernel reads the whole state (moments, sums, checkpoint): the
+// host Blocks' current values into their device storage.
+lbm_status host_push(lbm_ctx* c) { return hetero(c) ? host_copy(c, true) : LBM_OK; }
+
+// After the device wrote the whole state (initialisation, geometry,
+// checkpoint): link masks and state of the host Blocks to the host.
+lbm_status host_pull(lbm_ctx* c) {
+  if (!hetero(c)) return LBM_OK;
+  c->hmask.clear();
+  for (int j : c->host_ids) {
+    BlockDev& H = c->hbh[j];
+    const BlockDev& B = c->bh[j];
+    H.mask = -1;
+    if (c->has_mask && B.mask >= 0) {
+      const size_t n = (size_t)B.dim[0] * B.dim[1] * B.dim[2];
+      H.mask = (long long)c->hmask.size();
+      c->hmask.resize(c->hmask.size() + n);
+      HIPCHK(hipMemcpy(c->hmask.data() + H.mask, c->d_mask + B.mask, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    }
+  }
+  return host_copy(c, false);
+}
+
+// Free the heterogeneous set-up (state stays where it is: call host_push
+// first to keep it).
+void host_release(lbm_ctx* c) {
+  if (c->pool) host_pool_destroy(c->pool);
+  c->pool = nullptr;
+  for (void*& h : c->hgrid) {
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+  }
+  for (void** h : {&c->h_xdn, &c->h_xup}) {
+    if (*h) (void)hipHostFree(*h);
+    *h = nullptr;
+  }
+  for (void** d : {(void**)&c->d_t_dd, (void**)&c->d_t_dh, (void**)&c->d_t_hd, &c->d_xdn, &c->d_xup,
+                   (void**)&c->d_sweep_items}) {
+    if (*d) dfree(c, *d);
+    *d = nullptr;
+  }
+  c->sweep_items_cap = 0;
+  c->host_ids.clear();
+  c->on_host.assign(c->bh.size(), 0);
+  c->hbh.clear();
+  c->hmask.clear();
+  c->sweep_items_h.clear();
+  c->t_dd.clear();
+  c->t_dh.clear();
+  c->t_hd.clear();
+  c->t_hh.clear();
+  c->xdn_elems = c->xup_elems = 0;
+}
+
+lbm_status upload_tasks(lbm_ctx* c, const std::vector<XchgTask>& h, XchgTask** d) {
+  if (h.empty()) return LBM_OK;
+  *d = (XchgTask*)dalloc(c, h.size() * sizeof(XchgTask));
+  if (!*d) return fail(LBM_ENOMEM, "exchange task allocation failed");
+  HIPCHK(hipMemcpy(*d, h.data(), h.size() * sizeof(XchgTask), hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+// Assign the Blocks in ids to the host CPU (state copied over) and build the
+// exchange between the two memories.
+lbm_status host_setup(lbm_ctx* c, const std::vector<int>& ids, int threads) {
+  c->on_host.assign(c->bh.size(), 0);
+  for (int j : ids) c->on_host[j] = 1;
+  c->host_ids = ids;
+  std::sort(c->host_ids.begin(), c->host_ids.end());
+  // host pools: the Blocks' spans one after the other, page-aligned
+  c->hbh = c->bh;
+  long long hoff = 0;
+  for (int j : c->host_ids) {
+    c->hbh[j].base = hoff;
+    hoff = roundup(hoff + (long long)span_elems(c->bh[j]), 4096 / c->sbytes);
+  }
+  for (void*& h : c->hgrid)
+    if (hipHostMalloc(&h, (size_t)hoff * c->sbytes, hipHostMallocDefault) != hipSuccess) {
+      h = nullptr;
+      return fail(LBM_ENOMEM, "pinned host allocation for the host Blocks failed");
+    }
+  // exchange tasks by the sides of sender and receiver; the buffers hold
+  // 5 values per task cell
+  for (XchgTask t : c->tasks_h) {
+    const bool hs = c->on_host[c->nbh[(size_t)t.dst * 27 + t.d].id] != 0, hr = c->on_host[t.dst] != 0;
+    if (!hs && !hr) {
+      c->t_dd.push_back(t);
+    } else if (!hs && hr) {
+      t.bo = (int)c->xdn_elems;
+      c->xdn_elems += 5 * (size_t)(t.l1 - t.l0);
+      c->t_dh.push_back(t);
+    } else if (hs && !hr) {
+      t.bo = (int)c->xup_elems;
+      c->xup_elems += 5 * (size_t)(t.l1 - t.l0);
+      c->t_hd.push_back(t);
+    } else {
+      c->t_hh.push_back(t);
+    }
+  }
+  if (c->xdn_elems + c->xup_elems >= (1ull << 31)) return fail(LBM_EINVAL, "exchange buffers too large");
+  lbm_status st = upload_tasks(c, c->t_dd, &c->d_t_dd);
+  if (st == LBM_OK) st = upload_tasks(c, c->t_dh, &c->d_t_dh);
+  if (st == LBM_OK) st = upload_tasks(c, c->t_hd, &c->d_t_hd);
+  if (st != LBM_OK) return st;
+  const size_t nd = std::max<size_t>(1, c->xdn_elems) * c->sbytes, nu = std::max<size_t>(1, c->xup_elems) * c->sbytes;
+  c->d_xdn = dalloc(c, nd);
+  c->d_xup = dalloc(c, nu);
+  if (!c->d_xdn || !c->d_xup) return fail(LBM_ENOMEM, "exchange buffer allocation failed");
+  if (hipHostMalloc(&c->h_xdn, nd, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&c->h_xup, nu, hipHostMallocDefault) != hipSuccess)
+    return fail(LBM_ENOMEM, "pinned exchange buffer allocation failed");
+  build_items(c);
+  st = upload_items(c);
+  if (st != LBM_OK) return st;
+  if (threads <= 0) threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+  c->pool = host_pool_create(threads);
+  return host_pull(c);
+}
+
+struct HostTimes {
+  double gpu = 0.0, cpu = 0.0, xchg = 0.0, step = 0.0;
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// One time step of a heterogeneous run: the GPU sweeps its Blocks while the
+// host threads sweep theirs; then the exchange: host senders packed into the
+// up buffer and unpacked on the GPU, GPU pairs by the copy kernel, GPU
+// senders packed on the GPU and unpacked on the host, host pairs on the host.
+// ev: two events for the GPU sweep time (NULL: untimed).
+lbm_status host_step(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
+  const int from = c->cur, to = 1 - c->cur;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (tm) HIPCHK(hipEventRecord(ev[0], c->stream));
+  enqueue_sweep(c, from, c->stream);
+  if (tm) HIPCHK(hipEventRecord(ev[1], c->stream));
+  host_sweep(c->pool, c->prec, c->f64math, c->hgrid[from], c->hgrid[to], c->hbh.data(), c->host_ids.data(),
+             (int)c->host_ids.size(), c->has_mask ? c->hmask.data() : nullptr, c->geo, c->phd, c->phf);
+  std::chrono::steady_clock::time_point t1;
+  if (tm) {
+    tm->cpu += ms_since(t0);
+    HIPCHK(hipEventSynchronize(ev[1]));
+    t1 = std::chrono::steady_clock::now();
+  }
+  host_exchange(c->pool, c->prec, 1, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_hd.data(), (int)c->t_hd.size(),
+                c->h_xup);
+  host_exchange(c->pool, c->prec, 0, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_hh.data(), (int)c->t_hh.size(),
+                nullptr);
+  if (!c->t_hd.empty()) {
+    HIPCHK(hipMemcpyAsync(c->d_xup, c->h_xup, c->xup_elems * c->sbytes, hipMemcpyHostToDevice, c->stream));
+    launch_exchange_buf(c->prec, 2, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_hd, (int)c->t_hd.size(), c->d_xup,
+                        c->stream);
+  }
+  launch_exchange(c->prec, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dd, (int)c->t_dd.size(), c->stream);
+  if (!c->t_dh.empty()) {
+    launch_exchange_buf(c->prec, 1, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dh, (int)c->t_dh.size(), c->d_xdn,
+                        c->stream);
+    HIPCHK(hipMemcpyAsync(c->h_xdn, c->d_xdn, c->xdn_elems * c->sbytes, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  host_exchange(c->pool, c->prec, 2, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_dh.data(), (int)c->t_dh.size(),
+                c->h_xdn);
+  if (tm) {
+    float g = 0.f;
+    HIPCHK(hipEventElapsedTime(&g, ev[0], ev[1]));
+    tm->gpu += g;
+    tm->xchg += ms_since(t1);
+    tm->step += ms_since(t0);
+  }
+  c->cur = to;
+  c->steps += 1;
+  return LBM_OK;
+}
+
+lbm_status host_steps(lbm_ctx* c, long long n, HostTimes* tm) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  lbm_status st = LBM_OK;
+  if (tm)
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) st = fail(LBM_EDEVICE, "hipEventCreate failed");
+  for (long long k = 0; k < n && st == LBM_OK; ++k) st = host_step(c, tm, ev);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return st;
+}
+
 lbm_status run_steps(lbm_ctx* c, long long n) {
   if (n <= 0) return LBM_OK;
+  if (hetero(c)) return host_steps(c, n, nullptr);
   if (c->sched.graph_steps > 0) {
     lbm_status s = ensure_graphs(c);
     if (s != LBM_OK) return s;
@@ -514,6 +767,8 @@ long long row_pad_lines(const lbm_params& p, long long row_bytes) {
 }
 
 lbm_status reduce(lbm_ctx* c, int want_prev, double out[6]) {
+  lbm_status hs = host_push(c);
+  if (hs != LBM_OK) return hs;
   double hc[3], hp[3];
   half_force(c, c->steps >= 1, hc);
   half_force(c, c->steps >= 2, hp);
@@ -591,6 +846,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_OK;
   drop_graphs(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  host_release(c);
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -750,9 +1006,13 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   const long long align = 128 / c->sbytes;  // elements per 128-byte line
   long long off = 0;
   c->bh.resize(nblocks);
+  c->on_host.assign(nblocks, 0);
+  c->bfluid.assign(nblocks, 0);
   for (int j = 0; j < nblocks; ++j) {
     BlockDev& B = c->bh[j];
     std::memset(&B, 0, sizeof(B));
+    c->bfluid[j] = (long long)(blocks[j].hi[0] - blocks[j].lo[0]) * (blocks[j].hi[1] - blocks[j].lo[1]) *
+                   (blocks[j].hi[2] - blocks[j].lo[2]);
     for (int k = 0; k < 3; ++k) {
       B.org[k] = blocks[j].lo[k];
       B.dim[k] = blocks[j].hi[k] - blocks[j].lo[k];
@@ -923,7 +1183,18 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   c->cur = 0;
   c->steps = 0;
   c->mark_steps = -1;
-  return LBM_OK;
+  // fluid cells per Block (static load balance)
+  for (size_t j = 0; j < c->bh.size(); ++j) {
+    const lbm_aabb& A = c->aabb[j];
+    long long nf = (long long)(A.hi[0] - A.lo[0]) * (A.hi[1] - A.lo[1]) * (A.hi[2] - A.lo[2]);
+    if (solid)
+      for (int z = A.lo[2]; z < A.hi[2]; ++z)
+        for (int y = A.lo[1]; y < A.hi[1]; ++y)
+          for (int x = A.lo[0]; x < A.hi[0]; ++x)
+            nf -= solid[((long long)z * c->geo.n[1] + y) * c->geo.n[0] + x] != 0;
+    c->bfluid[j] = nf;
+  }
+  return host_pull(c);
 }
 
 lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
@@ -940,7 +1211,7 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 0;
   c->mark_steps = -1;
-  return LBM_OK;
+  return host_pull(c);
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
@@ -952,6 +1223,15 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms) {
   if (!c || !sweep_ms || !exchange_ms) return fail(LBM_EINVAL, "NULL argument");
   if (n < 1 || n > 100000) return fail(LBM_EINVAL, "step count must be in [1, 100000]");
+  if (hetero(c)) {
+    // wall-clock phases: both sweeps, then the exchange
+    HostTimes tm;
+    lbm_status st = host_steps(c, n, &tm);
+    if (st != LBM_OK) return st;
+    *sweep_ms = (tm.step - tm.xchg) / (double)n;
+    *exchange_ms = tm.xchg / (double)n;
+    return LBM_OK;
+  }
   const bool ex = c->sched.fused_exchange != 1 || has_open(c);
   const size_t ne = (size_t)n * (ex ? 3 : 2);
   std::vector<hipEvent_t> ev(ne, nullptr);
@@ -993,6 +1273,8 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* excha
 
 lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_device) {
   if (!c || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status hs = host_push(c);
+  if (hs != LBM_OK) return hs;
   const size_t N = (size_t)c->n_cells;
   double hg[3];
   half_force(c, c->steps >= 1, hg);
@@ -1030,6 +1312,8 @@ lbm_status lbm_residual_mark(lbm_ctx* c) {
     c->d_umark = (double*)dalloc(c, 4 * (size_t)c->n_cells * sizeof(double));
     if (!c->d_umark) return fail(LBM_ENOMEM, "velocity snapshot allocation failed");
   }
+  lbm_status hs = host_push(c);
+  if (hs != LBM_OK) return hs;
   double hg[3];
   half_force(c, c->steps >= 1, hg);
   launch_macro(c->prec, c->grid[c->cur], cell_args(c), c->p.rho0, hg, c->d_umark, c->d_umark + c->n_cells,
@@ -1065,6 +1349,8 @@ lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]) {
 
 lbm_status lbm_get_state(lbm_ctx* c, void* f, int32_t as_fp64) {
   if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status hs = host_push(c);
+  if (hs != LBM_OK) return hs;
   const size_t N = (size_t)c->n_cells;
   const size_t bytes = (size_t)kQ * N * (as_fp64 ? sizeof(double) : c->sbytes);
   lbm_status s = ensure_stage(c, bytes);
@@ -1089,7 +1375,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 1;
   c->mark_steps = -1;
-  return LBM_OK;
+  return host_pull(c);
 }
 
 lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s) {
@@ -1136,8 +1422,137 @@ lbm_status lbm_info_get(lbm_ctx* c, lbm_info* info) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_host_blocks(lbm_ctx* c, const int32_t* ids, int32_t n, int32_t threads) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  const int nb = (int)c->bh.size();
+  if (n < 0 || n > nb || (n > 0 && !ids)) return fail(LBM_EINVAL, "host Block list: bad count or NULL list");
+  if (threads < 0 || threads > 1024) return fail(LBM_EINVAL, "threads must be in [0, 1024]");
+  std::vector<int> list(ids, ids + n);
+  std::vector<char> seen(nb, 0);
+  for (int j : list) {
+    if (j < 0 || j >= nb || seen[j]) return fail(LBM_EINVAL, "host Block ids must be distinct BlockIDs");
+    seen[j] = 1;
+  }
+  if (n > 0 && c->prec > 1) return fail(LBM_EINVAL, "host Blocks hold FP64 or FP32 storage");
+  if (n > 0 && has_open(c)) return fail(LBM_EINVAL, "host Blocks need a lattice without open faces");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  // the whole state back on the device, then the new split
+  lbm_status st = host_push(c);
+  if (st != LBM_OK) return st;
+  host_release(c);
+  build_items(c);
+  st = upload_items(c);
+  if (st != LBM_OK || n == 0) return st;
+  st = host_setup(c, list, threads);
+  if (st != LBM_OK) {
+    host_release(c);
+    build_items(c);
+    (void)upload_items(c);
+  }
+  return st;
+}
+
+lbm_status lbm_step_host_timed(lbm_ctx* c, int64_t n, double* gpu_sweep_ms, double* cpu_sweep_ms,
+                               double* exchange_ms, double* step_ms) {
+  if (!c || !gpu_sweep_ms || !cpu_sweep_ms || !exchange_ms || !step_ms) return fail(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > 100000) return fail(LBM_EINVAL, "step count must be in [1, 100000]");
+  if (!hetero(c)) return fail(LBM_ESTATE, "no Block runs on the host");
+  HostTimes tm;
+  lbm_status st = host_steps(c, n, &tm);
+  if (st != LBM_OK) return st;
+  *gpu_sweep_ms = tm.gpu / (double)n;
+  *cpu_sweep_ms = tm.cpu / (double)n;
+  *exchange_ms = tm.xchg / (double)n;
+  *step_ms = tm.step / (double)n;
+  return LBM_OK;
+}
+
+lbm_status lbm_balance_host_blocks(lbm_ctx* c, int32_t threads, int32_t trial_steps, int32_t* n_host,
+                                   double* ms_gpu_only, double* ms_balanced) {
+  if (!c || !n_host) return fail(LBM_EINVAL, "NULL argument");
+  if (trial_steps < 1 || trial_steps > 10000) return fail(LBM_EINVAL, "trial_steps must be in [1, 10000]");
+  if (threads < 0 || threads > 1024) return fail(LBM_EINVAL, "threads must be in [0, 1024]");
+  if (c->prec > 1 || has_open(c)) return fail(LBM_EINVAL, "host Blocks need FP64/FP32 storage and no open faces");
+  const int nb = (int)c->bh.size();
+  auto wall = [&](double* ms) -> lbm_status {
+    lbm_status s = run_steps(c, 2);
+    if (s != LBM_OK) return s;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    s = run_steps(c, trial_steps);
+    if (s != LBM_OK) return s;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *ms = ms_since(t0) / trial_steps;
+    return LBM_OK;
+  };
+  // every Block on the GPU, and the state saved: the trials advance a copy
+  // of the simulation
+  lbm_status st = lbm_set_host_blocks(c, nullptr, 0, 0);
+  if (st != LBM_OK) return st;
+  const size_t gbytes = c->grid_elems * c->sbytes;
+  void* save = dalloc(c, 2 * gbytes);
+  if (!save) return fail(LBM_ENOMEM, "balance backup allocation failed");
+  HIPCHK(hipMemcpyAsync(save, c->grid[0], gbytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync((char*)save + gbytes, c->grid[1], gbytes, hipMemcpyDeviceToDevice, c->stream));
+  const int cur0 = c->cur;
+  const long long steps0 = c->steps;
+  double tg = 0.0, th = 0.0;
+  int k = 0;
+  st = wall(&tg);
+  // the CPU's rate on the last Block of the list
+  int32_t last = nb - 1;
+  if (st == LBM_OK) st = lbm_set_host_blocks(c, &last, 1, threads);
+  if (st == LBM_OK) st = run_steps(c, 2);
+  double g = 0, cpu = 0, x = 0, sm = 0;
+  if (st == LBM_OK) st = lbm_step_host_timed(c, trial_steps, &g, &cpu, &x, &sm);
+  if (st == LBM_OK) {
+    const double rate_c = (double)std::max(1LL, c->bfluid[last]) / std::max(cpu, 1e-6);
+    const double rate_g = (double)std::max(1LL, c->n_fluid) / std::max(tg, 1e-6);
+    // the last k Blocks of the list, k as large as keeps the CPU's sweep no
+    // longer than the GPU's share (the Block counts per process of Sec. 5.3)
+    long long fh = 0;
+    while (k < nb - 1) {
+      const long long f2 = fh + c->bfluid[nb - 1 - k];
+      if ((double)f2 / rate_c > (double)(c->n_fluid - f2) / rate_g) break;
+      fh = f2;
+      ++k;
+    }
+    th = sm;  // k = 0: one Block on the host already outruns the GPU
+    if (k > 0) {
+      std::vector<int32_t> ids;
+      for (int j = nb - k; j < nb; ++j) ids.push_back(j);
+      st = lbm_set_host_blocks(c, ids.data(), k, threads);
+      if (st == LBM_OK) st = wall(&th);
+    }
+    if (k > 0 && th >= tg) k = 0;
+  }
+  // restore the simulation, then apply the split
+  lbm_status s2 = lbm_set_host_blocks(c, nullptr, 0, 0);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipMemcpyAsync(c->grid[0], save, gbytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(c->grid[1], (char*)save + gbytes, gbytes, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  dfree(c, save);
+  c->cur = cur0;
+  c->steps = steps0;
+  if (st == LBM_OK) st = s2;
+  if (st != LBM_OK) return st;
+  if (k > 0) {
+    std::vector<int32_t> ids;
+    for (int j = nb - k; j < nb; ++j) ids.push_back(j);
+    st = lbm_set_host_blocks(c, ids.data(), k, threads);
+    if (st != LBM_OK) return st;
+  }
+  *n_host = k;
+  if (ms_gpu_only) *ms_gpu_only = tg;
+  if (ms_balanced) *ms_balanced = th;
+  return LBM_OK;
+}
+
 lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps, lbm_schedule* chosen) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (hetero(c)) return fail(LBM_EINVAL, "the autotuner times schedules with every Block on the GPU");
   if (trial_steps < 1) trial_steps = 10;
   // problem signature
   std::ostringstream key;

@@ -76,7 +76,8 @@ class lbm_info(ctypes.Structure):
 SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step",
            "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
            "lbm_sums", "lbm_get_state", "lbm_set_state",
-           "lbm_get_schedule", "lbm_set_schedule", "lbm_autotune", "lbm_info_get", "lbm_destroy",
+           "lbm_get_schedule", "lbm_set_schedule", "lbm_set_host_blocks", "lbm_step_host_timed",
+           "lbm_balance_host_blocks", "lbm_autotune", "lbm_info_get", "lbm_destroy",
            "lbm_strerror", "lbm_last_error", "lbm_bw_probe", "lbm_hbm_probe"]
 
 _lib = None
@@ -113,6 +114,9 @@ def load(path=LIB_PATH):
         "lbm_set_state": [P, P, ctypes.c_int32],
         "lbm_get_schedule": [P, ctypes.POINTER(lbm_schedule)],
         "lbm_set_schedule": [P, ctypes.POINTER(lbm_schedule)],
+        "lbm_set_host_blocks": [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32],
+        "lbm_step_host_timed": [P, ctypes.c_int64, dp, dp, dp, dp],
+        "lbm_balance_host_blocks": [P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp, dp],
         "lbm_autotune": [P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(lbm_schedule)],
         "lbm_info_get": [P, ctypes.POINTER(lbm_info)],
         "lbm_destroy": [P],
@@ -226,6 +230,29 @@ def lbm_get_schedule(ctx):
 
 def lbm_set_schedule(ctx, s):
     _check(load().lbm_set_schedule(ctx, ctypes.byref(s)), "lbm_set_schedule")
+
+
+def lbm_set_host_blocks(ctx, ids, threads=0):
+    ids = [int(j) for j in ids]
+    arr = (ctypes.c_int32 * max(1, len(ids)))(*ids)
+    _check(load().lbm_set_host_blocks(ctx, arr if ids else None, len(ids), int(threads)), "lbm_set_host_blocks")
+
+
+def lbm_step_host_timed(ctx, n):
+    """n heterogeneous steps: mean (GPU sweep, host sweep, exchange, step) ms."""
+    v = [ctypes.c_double() for _ in range(4)]
+    _check(load().lbm_step_host_timed(ctx, int(n), *[ctypes.byref(x) for x in v]), "lbm_step_host_timed")
+    return tuple(x.value for x in v)
+
+
+def lbm_balance_host_blocks(ctx, threads=0, trial_steps=20):
+    """Static load balance: (host Block count k, ms per step GPU alone, ms per step of the split tried)."""
+    k = ctypes.c_int32()
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(load().lbm_balance_host_blocks(ctx, int(threads), int(trial_steps), ctypes.byref(k), ctypes.byref(a),
+                                          ctypes.byref(b)), "lbm_balance_host_blocks")
+    return k.value, a.value, b.value
 
 
 def lbm_autotune(ctx, cache_path=None, trial_steps=10):
@@ -443,6 +470,19 @@ class Lattice:
 
     def autotune(self, cache_path=None, trial_steps=10):
         return lbm_autotune(self.ctx, cache_path, trial_steps).as_dict()
+
+    def set_host_blocks(self, ids, threads=0):
+        """Run the Blocks with these BlockIDs on the host CPU (Sec. 4.5); [] returns all to the GPU."""
+        lbm_set_host_blocks(self.ctx, ids, threads)
+
+    def step_host_timed(self, n):
+        """n steps with host Blocks: mean (GPU sweep, host sweep, exchange, whole step) in ms."""
+        return lbm_step_host_timed(self.ctx, n)
+
+    def balance_host_blocks(self, threads=0, trial_steps=20):
+        """Static load balance between the GPU and the host CPU; returns
+        (k, ms GPU alone, ms with the split tried), the last k Blocks on the host."""
+        return lbm_balance_host_blocks(self.ctx, threads, trial_steps)
 
     def info(self):
         return lbm_info_get(self.ctx).as_dict()

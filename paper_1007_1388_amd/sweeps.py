@@ -5,6 +5,7 @@
   python -m paper_1007_1388_amd.sweeps open   [--steps 200]   # open x faces against periodic x
   python -m paper_1007_1388_amd.sweeps pad    [--steps 200]   # odd Block sizes and row padding
   python -m paper_1007_1388_amd.sweeps hbm                    # HBM ceilings of read, write, copy
+  python -m paper_1007_1388_amd.sweeps hetero [--steps 50]    # host-CPU Blocks next to the GPU's
 
 size:   periodic cube N^3 (N = 64..512 step 32) as one Block, FP32 and FP64
         storage, started from rest with g_x = 1e-6, tau 0.8: MLUPS against N,
@@ -26,6 +27,12 @@ hbm:    read-only, write-only and copy streams over 2 GiB buffers (well past
         streaming or ordinary, several grid sizes: the attainable bandwidth
         of each pattern (lbm_hbm_probe), against which the sweep (one read
         and one write of every value, the copy pattern) is read.
+hetero: the porous 512x256x256 channel in its uneven Blocks, FP32 (Sec. 5.3's
+        heterogeneous study on one node): the GPU alone, then the last k
+        Blocks on the host CPU (k = 1, 2, 4, 8, 16, 16 threads) with the GPU
+        sweep, host sweep, exchange and whole-step times; the host sweep's
+        rate against its thread count on the last Block; and the static load
+        balance (lbm_balance_host_blocks).
 open:   a 512x256x256 duct (y periodic, z walls), FP32: x periodic with a
         body force against a velocity inlet and a pressure outlet on the x
         faces, as one Block and as 4 Blocks along x; the second column of
@@ -137,6 +144,55 @@ def hbm_sweep(reps=10):
                           flush=True)
 
 
+def hetero_sweep(steps, threads=16):
+    import torch
+    p = inputs.preset("porous512")
+    blocks = inputs.uneven_blocks(p["dims"], p["block_edges"], seed=0)
+    solid = inputs.porous_spheres(p["dims"], p["solid_fraction"], p["radius"], seed=0)
+    lat = lbm.Lattice(p["dims"], blocks=blocks, walls=p["walls"], tau=p["tau"], force=p["force"], precision="f32")
+    lat.set_geometry(solid)
+    nb = len(blocks)
+    nf = lat.info()["n_fluid"]
+    lat.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    print(json.dumps(dict(study="hetero", case="gpu alone", blocks=nb, host_blocks=0, step_ms=round(ms, 4),
+                          mlups=round(nf / ms / 1e3, 1))), flush=True)
+    # host sweep rate against threads, last Block
+    for th in (1, 2, 4, 8, 16):
+        lat.set_host_blocks([nb - 1], threads=th)
+        lat.step(2)
+        g, c, x, s = lat.step_host_timed(max(5, steps // 5))
+        fh = _fluid(solid, blocks[nb - 1:])
+        print(json.dumps(dict(study="hetero", case="host rate", threads=th, host_fluid=fh, cpu_ms=round(c, 4),
+                              host_mlups=round(fh / c / 1e3, 1))), flush=True)
+    for k in (1, 2, 4, 8, 16):
+        ids = list(range(nb - k, nb))
+        lat.set_host_blocks(ids, threads=threads)
+        lat.step(2)
+        g, c, x, s = lat.step_host_timed(steps)
+        fh = _fluid(solid, blocks[nb - k:])
+        print(json.dumps(dict(study="hetero", case="split", threads=threads, host_blocks=k, host_fluid=fh,
+                              gpu_sweep_ms=round(g, 4), cpu_sweep_ms=round(c, 4), exchange_ms=round(x, 4),
+                              step_ms=round(s, 4), mlups=round(nf / s / 1e3, 1))), flush=True)
+    lat.set_host_blocks([])
+    k, tg, th = lat.balance_host_blocks(threads=threads, trial_steps=steps)
+    print(json.dumps(dict(study="hetero", case="balance", threads=threads, host_blocks=k, gpu_alone_ms=round(tg, 4),
+                          split_ms=round(th, 4))), flush=True)
+    lat.close()
+
+
+def _fluid(solid, blocks):
+    n = 0
+    for lo, hi in blocks:
+        # solid is [z][y][x]
+        n += int((solid[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] == 0).sum())
+    return n
+
+
 def open_sweep(steps):
     dims = (512, 256, 256)
     opn = {"-x": ("velocity", (0.02, 0.0, 0.0)), "+x": ("pressure", 1.0)}
@@ -152,7 +208,7 @@ def open_sweep(steps):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["size", "blocks", "open", "pad", "hbm"])
+    ap.add_argument("study", choices=["size", "blocks", "open", "pad", "hbm", "hetero"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--sizes", default="64-512:32")
     args = ap.parse_args()
@@ -168,6 +224,8 @@ def main():
         pad_sweep(args.steps)
     elif args.study == "hbm":
         hbm_sweep()
+    elif args.study == "hetero":
+        hetero_sweep(args.steps)
     else:
         block_sweep(args.steps)
 

@@ -124,6 +124,11 @@ def test_null_arguments_rejected():
     assert lib.lbm_residual_mark(None) == lbm.LBM_EINVAL
     assert lib.lbm_residual_since_mark(None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_destroy(None) == lbm.LBM_OK
+    assert lib.lbm_set_host_blocks(None, None, 0, 0) == lbm.LBM_EINVAL
+    d = ctypes.c_double()
+    assert lib.lbm_step_host_timed(None, 1, *[ctypes.byref(d)] * 4) == lbm.LBM_EINVAL
+    k = ctypes.c_int32()
+    assert lib.lbm_balance_host_blocks(None, 0, 10, ctypes.byref(k), None, None) == lbm.LBM_EINVAL
     assert lib.lbm_bw_probe(None, None, 16, 1, None, None) == lbm.LBM_EINVAL
     for bad in [(3, 1, 1, None, 1, 16, 0, 1, None), (0, 3, 1, 1, 1, 16, 0, 1, None), (0, 1, 1, None, 1, 16, 0, 1, None),
                 (2, 1, 1, 1, 1, 24, 0, 1, None), (1, 1, 1, None, 1, 16, 0, 0, None)]:

@@ -234,9 +234,9 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
  * with the same layout as on the GPU, and `threads` host threads (0: up to
  * 16) sweep them while the GPU sweeps its Blocks.  Values that cross between
  * a host and a GPU Block each step go through exchange buffers of one format
- * that both sides pack and unpack; the ghost exchange among GPU Blocks runs
- * in the copy kernel (fused_exchange is not used) and steps are launched
- * one by one (graph_steps is not used).  The host sweep repeats the GPU
+ * that both sides pack and unpack; the ghost exchange among GPU Blocks
+ * follows the schedule's fused_exchange, and steps are launched one by one
+ * (graph_steps is not used).  The host sweep repeats the GPU
  * arithmetic operation for operation, so results equal the all-GPU run bit
  * for bit.  n = 0 returns every Block to the GPU.  The state is carried
  * over; lbm_macroscopic, lbm_residual*, lbm_sums and lbm_get_state copy the

@@ -104,58 +104,78 @@ int host_pool_threads(const HostPool* p) { return p ? p->n : 0; }
 namespace {
 
 // ------------------------------------------------------------------ sweep
-// One x-row (y, z) of Block B.  T: storage type; C: arithmetic type; HYB:
-// FP32 storage with FP32 arithmetic, whose velocity and odd parts are kept
-// in FP64 (the GPU's mixed mode).
+// One x-row (y, z) of Block B in three passes over row buffers, so that the
+// collision runs as one branch-free loop over x that the compiler turns
+// into SIMD code (element-wise, so each cell rounds exactly as alone):
+//   pull:     W[i][x] = value cell x receives along e_i (shifted row copies;
+//             the x-ghost slot or the wrapped row end at the row ends; the
+//             cell's own f*_ibar across obstacle links),
+//   collide:  O[i][x] from W (solid cells: zeros), stored to the dst rows,
+//   bounce:   rows on a wall face only, f*_q to the slot (x + e_q, qbar).
+// T: storage type; C: arithmetic type; HYB: FP32 storage with FP32
+// arithmetic whose velocity and odd parts are kept in FP64 (the GPU's mixed
+// mode).  W and O are per-thread buffers of kQ * a elements.
 template <typename T, typename C, bool HYB>
 void sweep_row(const T* __restrict__ src, T* __restrict__ dst, const BlockDev& B, const uint32_t* mask,
-               const GridGeom& geo, const Phys<C>& ph, int y, int z) {
+               const GridGeom& geo, const Phys<C>& ph, int y, int z, C* __restrict__ W, T* __restrict__ O,
+               uint32_t* __restrict__ S) {
   const int a = B.dim[0], b = B.dim[1], c = B.dim[2];
   const bool wx = B.wrap & 1, wy = B.wrap & 2, wz = B.wrap & 4;
   const int gy = B.org[1] + y, gz = B.org[2] + z;
-  // source row and x-ghost slot of every direction
-  const T* srow[kQ];
-  T sxg[kQ];
+  const uint32_t* mrow = mask ? mask + B.mask + ((long long)z * b + y) * a : nullptr;
+
+  // ---- pull
   for (int i = 0; i < kQ; ++i) {
     const int zs = wz ? wrapc(z - kEz[i], c) : z - kEz[i];
     const int ys = wy ? wrapc(y - kEy[i], b) : y - kEy[i];
-    srow[i] = src + main_off(B, i, 0, ys, zs);
-    sxg[i] = kEx[i] != 0 && !wx ? src[xg_off(B, i, ys, zs)] : T(0);
+    const T* __restrict__ sr = src + main_off(B, i, 0, ys, zs);
+    C* __restrict__ w = W + (size_t)i * a;
+    if (kEx[i] == 0) {
+      for (int x = 0; x < a; ++x) w[x] = (C)sr[x];
+    } else if (kEx[i] > 0) {  // source x - 1
+      w[0] = (C)(wx ? sr[a - 1] : src[xg_off(B, i, ys, zs)]);
+      for (int x = 1; x < a; ++x) w[x] = (C)sr[x - 1];
+    } else {  // source x + 1
+      for (int x = 0; x < a - 1; ++x) w[x] = (C)sr[x + 1];
+      w[a - 1] = (C)(wx ? sr[0] : src[xg_off(B, i, ys, zs)]);
+    }
   }
-  T* drow[kQ];
-  for (int i = 0; i < kQ; ++i) drow[i] = dst + main_off(B, i, 0, y, z);
-  const bool loy = geo.fwall[2] && gy == 0, hiy = geo.fwall[3] && gy == geo.n[1] - 1;
-  const bool loz = geo.fwall[4] && gz == 0, hiz = geo.fwall[5] && gz == geo.n[2] - 1;
-  const bool moving =
-      geo.moving[0] | geo.moving[1] | geo.moving[2] | geo.moving[3] | geo.moving[4] | geo.moving[5];
-  const uint32_t* mrow = mask ? mask + B.mask + ((long long)z * b + y) * a : nullptr;
-
-  for (int x = 0; x < a; ++x) {
-    const uint32_t m = mrow ? mrow[x] : 0u;
-    if (m & kSolidBit) {
-      // solid cells store zeros (the GPU keeps whole lines written)
-      for (int i = 0; i < kQ; ++i) drow[i][x] = T(0);
-      continue;
-    }
-    C W[kQ];
-    for (int i = 0; i < kQ; ++i) {
-      const int xs = x - kEx[i];
-      T v;
-      if (xs >= 0 && xs < a) v = srow[i][xs];
-      else if (wx) v = srow[i][wrapc(xs, a)];
-      else v = sxg[i];
-      W[i] = (C)v;
-    }
+  // S[x]: all ones for a solid cell, else zero
+  for (int x = 0; x < a; ++x) S[x] = mrow && (mrow[x] & kSolidBit) ? ~0u : 0u;
+  if (mrow) {
     // obstacle links: the cell's own f*_ibar of the previous step
-    if (m)
+    for (int x = 0; x < a; ++x) {
+      const uint32_t m = mrow[x];
+      if (!(m & ~kSolidBit)) continue;
       for (int i = 1; i < kQ; ++i)
-        if ((m >> i) & 1u) W[i] = (C)src[main_off(B, kOpp[i], x, y, z)];
+        if ((m >> i) & 1u) W[(size_t)i * a + x] = (C)src[main_off(B, kOpp[i], x, y, z)];
+    }
+  }
 
+  // ---- collide
+  const C omega = ph.omega, omc = ph.omc, fcoef = ph.fcoef, rho0 = ph.rho0, rho0x3 = ph.rho0x3;
+  const C w0 = ph.w[0], w1 = ph.w[1], w7 = ph.w[7];
+  const C inv_rho0 = ph.inv_rho0, hg0 = ph.hg[0], hg1 = ph.hg[1], hg2 = ph.hg[2];
+  const C g0 = ph.g[0], g1 = ph.g[1], g2 = ph.g[2];
+  const double dinv = ph.dinv_rho0, dhg0 = ph.dhg[0], dhg1 = ph.dhg[1], dhg2 = ph.dhg[2];
+  const double domega = ph.domega, domc = ph.domc;
+  C c9g[kQ], c3w[kQ], cfa[kQ];
+  double dc3w[kQ], dcfa[kQ];
+  for (int i = 0; i < kQ; ++i) {
+    c9g[i] = ph.c9g[i];
+    c3w[i] = ph.c3w[wcls(i)];
+    cfa[i] = ph.cfa[i];
+    dc3w[i] = ph.dc3w[wcls(i)];
+    dcfa[i] = ph.dcfa[i];
+  }
+#pragma clang loop vectorize(enable)
+  for (int x = 0; x < a; ++x) {
+    C f[kQ];
+    for (int i = 0; i < kQ; ++i) f[i] = W[(size_t)i * a + x];
     // moments: drho = sum f~, rho0 u = sum e f~, plus half force
-    C d = W[0], jx = (C)0, jy = (C)0, jz = (C)0;
+    C d = f[0], jx = (C)0, jy = (C)0, jz = (C)0;
     for (int i = 1; i < kQ; i += 2) {
-      const C fa = W[i], fb = W[i + 1];
-      const C sp = fa + fb, dp = fa - fb;
+      const C sp = f[i] + f[i + 1], dp = f[i] - f[i + 1];
       d += sp;
       if (kEx[i] > 0) jx += dp;
       if (kEx[i] < 0) jx -= dp;
@@ -168,31 +188,32 @@ void sweep_row(const T* __restrict__ src, T* __restrict__ dst, const BlockDev& B
     C ux, uy, uz;
     double dux = 0.0, duy = 0.0, duz = 0.0;
     if constexpr (HYB) {
-      dux = std::fma((double)jx, ph.dinv_rho0, ph.dhg[0]);
-      duy = std::fma((double)jy, ph.dinv_rho0, ph.dhg[1]);
-      duz = std::fma((double)jz, ph.dinv_rho0, ph.dhg[2]);
+      dux = std::fma((double)jx, dinv, dhg0);
+      duy = std::fma((double)jy, dinv, dhg1);
+      duz = std::fma((double)jz, dinv, dhg2);
       ux = (C)dux;
       uy = (C)duy;
       uz = (C)duz;
     } else {
-      ux = std::fma(jx, ph.inv_rho0, ph.hg[0]);
-      uy = std::fma(jy, ph.inv_rho0, ph.hg[1]);
-      uz = std::fma(jz, ph.inv_rho0, ph.hg[2]);
+      ux = std::fma(jx, inv_rho0, hg0);
+      uy = std::fma(jy, inv_rho0, hg1);
+      uz = std::fma(jz, inv_rho0, hg2);
     }
     const C uu15 = (C)1.5 * std::fma(ux, ux, std::fma(uy, uy, uz * uz));
-    const C ug3 = ph.rho0x3 * std::fma(ux, ph.g[0], std::fma(uy, ph.g[1], uz * ph.g[2]));
-
+    const C ug3 = rho0x3 * std::fma(ux, g0, std::fma(uy, g1, uz * g2));
+    const bool solid = S[x] != 0u;
     T o[kQ];
     {
-      const C feq = ph.w[0] * std::fma(ph.rho0, -uu15, drho);
-      const C F = -ph.w[0] * ug3;
-      const C even = std::fma(ph.omega, feq, ph.fcoef * F);
+      const C feq = w0 * std::fma(rho0, -uu15, drho);
+      const C F = -w0 * ug3;
+      const C even = std::fma(omega, feq, fcoef * F);
       if constexpr (HYB)
-        o[0] = (T)std::fma(ph.domc, (double)W[0], (double)even);
+        o[0] = (T)std::fma(domc, (double)f[0], (double)even);
       else
-        o[0] = (T)std::fma(ph.omc, W[0], even);
+        o[0] = (T)std::fma(omc, f[0], even);
     }
     for (int i = 1; i < kQ; i += 2) {
+      const C wc = i < 7 ? w1 : w7;
       C eu = (C)0;
       double deu = 0.0;
       if constexpr (HYB) {
@@ -211,24 +232,39 @@ void sweep_row(const T* __restrict__ src, T* __restrict__ dst, const BlockDev& B
         if (kEz[i] > 0) eu += uz;
         if (kEz[i] < 0) eu -= uz;
       }
-      const C sym = ph.w[wcls(i)] * std::fma(ph.rho0, std::fma((C)4.5 * eu, eu, -uu15), drho);
-      const C Fs = std::fma(ph.c9g[i], eu, -ph.w[wcls(i)] * ug3);
-      const C even = std::fma(ph.omega, sym, ph.fcoef * Fs);
+      const C sym = wc * std::fma(rho0, std::fma((C)4.5 * eu, eu, -uu15), drho);
+      const C Fs = std::fma(c9g[i], eu, -wc * ug3);
+      const C even = std::fma(omega, sym, fcoef * Fs);
       if constexpr (HYB) {
-        const double odd = std::fma(ph.domega, ph.dc3w[wcls(i)] * deu, ph.dcfa[i]);
+        const double odd = std::fma(domega, dc3w[i] * deu, dcfa[i]);
         const double ev = (double)even;
-        o[i] = (T)std::fma(ph.domc, (double)W[i], ev + odd);
-        o[i + 1] = (T)std::fma(ph.domc, (double)W[i + 1], ev - odd);
+        o[i] = (T)std::fma(domc, (double)f[i], ev + odd);
+        o[i + 1] = (T)std::fma(domc, (double)f[i + 1], ev - odd);
       } else {
-        const C odd = std::fma(ph.omega, ph.c3w[wcls(i)] * eu, ph.cfa[i]);
-        o[i] = (T)std::fma(ph.omc, W[i], even + odd);
-        o[i + 1] = (T)std::fma(ph.omc, W[i + 1], even - odd);
+        const C odd = std::fma(omega, c3w[i] * eu, cfa[i]);
+        o[i] = (T)std::fma(omc, f[i], even + odd);
+        o[i + 1] = (T)std::fma(omc, f[i + 1], even - odd);
       }
     }
-    for (int i = 0; i < kQ; ++i) drow[i][x] = o[i];
+    // solid cells store zeros (the GPU keeps whole lines written)
+    for (int i = 0; i < kQ; ++i) O[(size_t)i * a + x] = solid ? T(0) : o[i];
+  }
+  for (int i = 0; i < kQ; ++i) {
+    T* __restrict__ dr = dst + main_off(B, i, 0, y, z);
+    const T* __restrict__ orow = O + (size_t)i * a;
+    for (int x = 0; x < a; ++x) dr[x] = orow[x];
+  }
 
-    // bounce-back at walls: f*_q(x) (plus the moving-wall term) goes to the
-    // slot (x + e_q, qbar) when x + e_q lies beyond a wall face
+  // ---- bounce-back at walls: f*_q(x) (plus the moving-wall term) goes to
+  // the slot (x + e_q, qbar) when x + e_q lies beyond a wall face
+  const bool loy = geo.fwall[2] && gy == 0, hiy = geo.fwall[3] && gy == geo.n[1] - 1;
+  const bool loz = geo.fwall[4] && gz == 0, hiz = geo.fwall[5] && gz == geo.n[2] - 1;
+  const bool xwalls = (geo.fwall[0] && B.org[0] == 0) || (geo.fwall[1] && B.org[0] + a == geo.n[0]);
+  if (!(loy | hiy | loz | hiz | xwalls)) return;
+  const bool moving =
+      geo.moving[0] | geo.moving[1] | geo.moving[2] | geo.moving[3] | geo.moving[4] | geo.moving[5];
+  for (int x = 0; x < a; ++x) {
+    if (mrow && (mrow[x] & kSolidBit)) continue;
     const int gx = B.org[0] + x;
     const bool lox = geo.fwall[0] && gx == 0, hix = geo.fwall[1] && gx == geo.n[0] - 1;
     if (!(lox | hix | loy | hiy | loz | hiz)) continue;
@@ -238,7 +274,7 @@ void sweep_row(const T* __restrict__ src, T* __restrict__ dst, const BlockDev& B
       const bool link = (ex > 0 && lox) || (ex < 0 && hix) || (ey > 0 && loy) || (ey < 0 && hiy) ||
                         (ez > 0 && loz) || (ez < 0 && hiz);
       if (!link) continue;
-      T v = o[q];
+      T v = O[(size_t)q * a + x];
       if (moving) {
         // the first moving face in the order -x, +x, -y, +y, -z, +z
         C cw = (C)0;
@@ -248,7 +284,7 @@ void sweep_row(const T* __restrict__ src, T* __restrict__ dst, const BlockDev& B
         if (ey < 0 && hiy && geo.moving[3]) cw = ph.corr[qb][3];
         if (ex > 0 && lox && geo.moving[0]) cw = ph.corr[qb][0];
         if (ex < 0 && hix && geo.moving[1]) cw = ph.corr[qb][1];
-        v = (T)((C)o[q] + cw);
+        v = (T)((C)v + cw);
       }
       const int zt = wz ? wrapc(z + kEz[q], c) : z + kEz[q];
       const int yt = wy ? wrapc(y + kEy[q], b) : y + kEy[q];
@@ -268,9 +304,14 @@ void sweep_all(HostPool* p, const T* src, T* dst, const BlockDev* blocks, const 
   for (int k = 0; k < nids; ++k)
     first[k + 1] = first[k] + (long long)blocks[ids[k]].dim[1] * blocks[ids[k]].dim[2];
   const long long nrows = first[nids];
+  int amax = 1;
+  for (int k = 0; k < nids; ++k) amax = std::max(amax, blocks[ids[k]].dim[0]);
   constexpr long long RUN = 4;
   std::atomic<long long> next(0);
   p->run([&](int) {
+    std::vector<C> W((size_t)kQ * amax);
+    std::vector<T> O((size_t)kQ * amax);
+    std::vector<uint32_t> S(amax);
     for (;;) {
       const long long r0 = next.fetch_add(RUN);
       if (r0 >= nrows) return;
@@ -280,7 +321,8 @@ void sweep_all(HostPool* p, const T* src, T* dst, const BlockDev* blocks, const 
         while (r >= first[k + 1]) ++k;
         const BlockDev& B = blocks[ids[k]];
         const long long lr = r - first[k];
-        sweep_row<T, C, HYB>(src, dst, B, mask, geo, ph, (int)(lr % B.dim[1]), (int)(lr / B.dim[1]));
+        sweep_row<T, C, HYB>(src, dst, B, mask, geo, ph, (int)(lr % B.dim[1]), (int)(lr / B.dim[1]), W.data(),
+                             O.data(), S.data());
       }
     }
   });
@@ -290,7 +332,7 @@ template <typename T>
 void exchange_tasks(HostPool* p, int mode, T* grid, const BlockDev* blocks, const NbrDev* nbr,
                     const XchgTask* tasks, int ntasks, T* buf) {
   std::atomic<int> next(0);
-  p->run([&](int) {
+  auto work = [&](int) {
     for (;;) {
       const int k = next.fetch_add(1);
       if (k >= ntasks) return;
@@ -323,7 +365,14 @@ void exchange_tasks(HostPool* p, int mode, T* grid, const BlockDev* blocks, cons
         }
       }
     }
-  });
+  };
+  // small exchanges stay on the calling thread (waking the pool costs more)
+  long long cells = 0;
+  for (int k = 0; k < ntasks; ++k) cells += tasks[k].l1 - tasks[k].l0;
+  if (cells < 2048)
+    work(0);
+  else
+    p->run(work);
 }
 
 }  // namespace

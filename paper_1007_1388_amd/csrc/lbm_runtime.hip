@@ -152,7 +152,8 @@ struct lbm_ctx {
   size_t sweep_items_cap = 0;
   // exchange tasks by (sender, receiver): GPU->GPU, GPU->host, host->GPU, host->host
   std::vector<XchgTask> t_dd, t_dh, t_hd, t_hh;
-  XchgTask *d_t_dd = nullptr, *d_t_dh = nullptr, *d_t_hd = nullptr;
+  std::vector<XchgTask> t_dd_rim;   // GPU->GPU rim tasks (x faces written by the sweep)
+  XchgTask *d_t_dd = nullptr, *d_t_dh = nullptr, *d_t_hd = nullptr, *d_t_dd_rim = nullptr;
   void *d_xdn = nullptr, *d_xup = nullptr, *h_xdn = nullptr, *h_xup = nullptr;
   size_t xdn_elems = 0, xup_elems = 0;
   std::vector<long long> bfluid;        // fluid cells per Block
@@ -452,10 +453,8 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   int grid = nitems;
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
-  // a heterogeneous run exchanges through the copy kernel and the buffers
-  const int fx = hetero(c) ? 0 : c->sched.fused_exchange;
-  launch_sweep(c->prec, c->f64math, c->has_mask, fx, c->sched.nontemporal != 0, cells_per_lane(c, c->sched), a,
-               c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
+  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange, c->sched.nontemporal != 0,
+               cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
 bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
@@ -556,8 +555,8 @@ void host_release(lbm_ctx* c) {
     if (*h) (void)hipHostFree(*h);
     *h = nullptr;
   }
-  for (void** d : {(void**)&c->d_t_dd, (void**)&c->d_t_dh, (void**)&c->d_t_hd, &c->d_xdn, &c->d_xup,
-                   (void**)&c->d_sweep_items}) {
+  for (void** d : {(void**)&c->d_t_dd, (void**)&c->d_t_dh, (void**)&c->d_t_hd, (void**)&c->d_t_dd_rim, &c->d_xdn,
+                   &c->d_xup, (void**)&c->d_sweep_items}) {
     if (*d) dfree(c, *d);
     *d = nullptr;
   }
@@ -568,6 +567,7 @@ void host_release(lbm_ctx* c) {
   c->hmask.clear();
   c->sweep_items_h.clear();
   c->t_dd.clear();
+  c->t_dd_rim.clear();
   c->t_dh.clear();
   c->t_hd.clear();
   c->t_hh.clear();
@@ -619,8 +619,11 @@ lbm_status host_setup(lbm_ctx* c, const std::vector<int>& ids, int threads) {
       c->t_hh.push_back(t);
     }
   }
+  for (const XchgTask& t : c->rim_h)
+    if (!c->on_host[c->nbh[(size_t)t.dst * 27 + t.d].id] && !c->on_host[t.dst]) c->t_dd_rim.push_back(t);
   if (c->xdn_elems + c->xup_elems >= (1ull << 31)) return fail(LBM_EINVAL, "exchange buffers too large");
   lbm_status st = upload_tasks(c, c->t_dd, &c->d_t_dd);
+  if (st == LBM_OK) st = upload_tasks(c, c->t_dd_rim, &c->d_t_dd_rim);
   if (st == LBM_OK) st = upload_tasks(c, c->t_dh, &c->d_t_dh);
   if (st == LBM_OK) st = upload_tasks(c, c->t_hd, &c->d_t_hd);
   if (st != LBM_OK) return st;
@@ -675,7 +678,13 @@ lbm_status host_step(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
     launch_exchange_buf(c->prec, 2, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_hd, (int)c->t_hd.size(), c->d_xup,
                         c->stream);
   }
-  launch_exchange(c->prec, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dd, (int)c->t_dd.size(), c->stream);
+  // GPU pairs as the schedule says: the copy kernel (fused_exchange 0), its
+  // rim after the sweep's x faces (2), or nothing after the fused sweep (1);
+  // the sweep's writes into a host Block's device copy are never read
+  if (c->sched.fused_exchange == 0)
+    launch_exchange(c->prec, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dd, (int)c->t_dd.size(), c->stream);
+  else if (c->sched.fused_exchange == 2)
+    launch_exchange(c->prec, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dd_rim, (int)c->t_dd_rim.size(), c->stream);
   if (!c->t_dh.empty()) {
     launch_exchange_buf(c->prec, 1, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dh, (int)c->t_dh.size(), c->d_xdn,
                         c->stream);

@@ -28,8 +28,10 @@ def cavity(dims=(14, 12, 13)):
                 tau=0.6)
 
 
-def run(case, steps, blocks, host=(), precision="f64", fp64_math=False, threads=3):
+def run(case, steps, blocks, host=(), precision="f64", fp64_math=False, threads=3, fused=None):
     lat = gpu_lattice(case, blocks=blocks, precision=precision, fp64_math=fp64_math)
+    if fused is not None:
+        lat.set_schedule(fused_exchange=fused)
     prepare(lat, case)
     if host:
         lat.set_host_blocks(list(host), threads=threads)
@@ -57,6 +59,17 @@ def test_host_blocks_bitwise_equal_gpu(precision, f64m, host):
     ra, ua = lat.macroscopic()
     rb, ub = ref.macroscopic()
     assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
+@pytest.mark.parametrize("fused", [0, 1, 2])
+def test_host_blocks_with_every_exchange_mode(fused):
+    """GPU pairs exchange as the schedule says (copy kernel, sweep-written x
+    faces plus rim, fully fused sweep) while host pairs use the buffers."""
+    case = porous(dims=(36, 18, 16), seed=9)
+    blocks = inputs.uniform_blocks(case["dims"], (3, 2, 2))
+    ref = run(case, 19, blocks, precision="f32", fused=0)
+    lat = run(case, 19, blocks, host=(1, 6, 10), precision="f32", fused=fused)
+    assert same_state(lat, ref)
 
 
 def test_moving_walls_on_the_host_match_oracle():

@@ -127,6 +127,25 @@ def test_moving_blocks_between_host_and_gpu_midrun():
         assert lat.residual() == ref.residual()
 
 
+def test_checkpoint_and_residual_snapshot_with_host_blocks():
+    """A checkpoint taken and restored while Blocks run on the host resumes
+    bit for bit; the velocity snapshot residual sees the host Blocks."""
+    case = porous(dims=(32, 16, 12), seed=4)
+    blocks = inputs.uniform_blocks(case["dims"], (2, 2, 1))
+    ref = run(case, 11, blocks, precision="f32")
+    lat = run(case, 11, blocks, host=(1, 2), precision="f32")
+    f = lat.get_state(as_fp64=False)
+    lat.step(5)
+    lat.set_state(f, as_fp64=False)
+    ref.set_state(ref.get_state(as_fp64=False), as_fp64=False)
+    lat.residual_mark()
+    ref.residual_mark()
+    lat.step(8)
+    ref.step(8)
+    assert same_state(lat, ref)
+    assert lat.residual_since_mark() == ref.residual_since_mark()
+
+
 def test_host_timing_and_balance_keep_the_state():
     case = porous(dims=(64, 32, 32), seed=1)
     blocks = inputs.uniform_blocks(case["dims"], (2, 2, 2))

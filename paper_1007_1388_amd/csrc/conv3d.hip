@@ -695,7 +695,17 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t Xs[2][CELLS * PC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Geo gx = a.gx, gy = a.gy;
-  int by = blockIdx.y;
+  // Work index from the linear workgroup id, XCD-aware: workgroups are
+  // dealt to the 8 XCDs in turn, so id L runs on XCD L % 8; consecutive
+  // indices (the weight tiles of one step range, which read the same dy and
+  // x data) are given to consecutive workgroups of one XCD and share its L2.
+  // The tail past the last multiple of 8 keeps its own index.
+  const int total = (int)gridDim.x, L8 = (int)blockIdx.x;
+  const int q8 = total / 8 * 8;
+  const int idx = L8 < q8 ? (L8 % 8) * (total / 8) + L8 / 8 : L8;
+  const int ntiles = 3 * a.nci * a.nco;
+  int by = idx % ntiles;
+  const int split = idx / ntiles;
   const int co_t = by % a.nco;
   by /= a.nco;
   const int ci_t = by % a.nci;
@@ -747,7 +757,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
 
   const __amdgpu_buffer_rsrc_t rx = rsrc_of(a.x, a.x_bytes);
   const __amdgpu_buffer_rsrc_t rd = rsrc_of(a.dy, a.dy_bytes);
-  const int s_begin = blockIdx.x * a.per_wg;
+  const int s_begin = split * a.per_wg;
   const int s_end = s_begin + a.per_wg < a.steps ? s_begin + a.per_wg : a.steps;
   // uniform step coordinates, advanced without branches
   int st = s_begin;
@@ -1198,7 +1208,7 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     const long long splits = (steps + per - 1) / per;
     a.steps = (int)steps;
     a.per_wg = (int)per;
-    const dim3 g((unsigned)splits, (unsigned)tiles);
+    const dim3 g((unsigned)(splits * tiles));
     if (stride == 1) {
       if (bmw == 32)
         hipLaunchKernelGGL((k_conv_wgrad_halo<1, 32>), g, b, 0, s, a);

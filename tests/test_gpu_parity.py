@@ -521,3 +521,28 @@ def test_unstable_run_is_reported():
     with pytest.raises(LBMError) as e:
         lat.sums()
     assert e.value.status == LBM_EUNSTABLE
+
+
+def test_repeated_create_destroy_returns_device_memory():
+    """Contexts of 128^3 (about 0.35 GB of grids each) created and destroyed
+    in a row, with geometry, a velocity snapshot and, on every other one,
+    a host Block: the device memory comes back every time."""
+    import torch
+    dims = (128, 128, 128)
+    solid = inputs.porous_spheres(dims, target_fraction=0.05, radius=(2, 4), seed=1)
+    case = channel(dims=dims, solid=solid, force=(1e-6, 0, 0), tau=0.8)
+    blocks = inputs.uniform_blocks(dims, (2, 1, 1))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    for k in range(8):
+        lat = run_gpu(case, 2, blocks=blocks, precision="f32")
+        lat.residual_mark()
+        if k % 2 == 0:
+            lat.set_host_blocks([1], threads=2)
+            lat.step(1)
+        lat.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free0 - free1 < (256 << 20), (free0 - free1) / 2**20

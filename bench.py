@@ -174,7 +174,7 @@ def main():
                     help="only run the copy probe on this many bytes (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the Block exchange between GPUs is a "
+        print("bench.py: the solver runs on one GPU only (the Block exchange between GPUs is a "
               "design, not code); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

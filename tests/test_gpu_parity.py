@@ -546,3 +546,19 @@ def test_repeated_create_destroy_returns_device_memory():
     torch.cuda.empty_cache()
     free1, _ = torch.cuda.mem_get_info()
     assert free0 - free1 < (256 << 20), (free0 - free1) / 2**20
+
+
+@pytest.mark.parametrize("precision,key", [("f32", "gpu_bytes_sp"), ("f64", "gpu_bytes_dp")])
+def test_reported_bytes_per_update_is_the_papers_model(precision, key):
+    """lbm_info's bytes per fluid-cell update (the roofline's algorithmic
+    bytes) is the model printed in Sec. 3.1 without obstacles, and adds the
+    4-byte link mask with them."""
+    from tests.test_golden import golden
+    g = golden("bytes_per_update.txt")
+    lat = run_gpu(channel(dims=(16, 8, 6)), 0, precision=precision)
+    assert lat.info()["bytes_per_update"] == g[key]
+    dims = (16, 8, 6)
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 2), seed=3)
+    lat2 = run_gpu(channel(dims=dims, solid=solid), 0, precision=precision)
+    i = lat2.info()
+    assert i["bytes_per_update"] == g[key] + 4.0 * i["n_cells"] / i["n_fluid"]

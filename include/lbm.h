@@ -236,7 +236,9 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
  * a host and a GPU Block each step go through exchange buffers of one format
  * that both sides pack and unpack; the ghost exchange among GPU Blocks
  * follows the schedule's fused_exchange, and steps are launched one by one
- * (graph_steps is not used).  The host sweep repeats the GPU
+ * (graph_steps is not used): each step's exchange is followed on the stream
+ * by the next GPU sweep while the host unpacks and sweeps.  lbm_step returns
+ * after the last step's exchange has arrived (synchronous with host Blocks).  The host sweep repeats the GPU
  * arithmetic operation for operation, so results equal the all-GPU run bit
  * for bit.  n = 0 returns every Block to the GPU.  The state is carried
  * over; lbm_macroscopic, lbm_residual*, lbm_sums and lbm_get_state copy the

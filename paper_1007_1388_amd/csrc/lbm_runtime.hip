@@ -156,6 +156,7 @@ struct lbm_ctx {
   XchgTask *d_t_dd = nullptr, *d_t_dh = nullptr, *d_t_hd = nullptr, *d_t_dd_rim = nullptr;
   void *d_xdn = nullptr, *d_xup = nullptr, *h_xdn = nullptr, *h_xup = nullptr;
   size_t xdn_elems = 0, xup_elems = 0;
+  hipEvent_t x_done = nullptr;          // the step's down buffer has arrived
   std::vector<long long> bfluid;        // fluid cells per Block
 };
 
@@ -567,6 +568,8 @@ lbm_status host_pull(lbm_ctx* c) {
 void host_release(lbm_ctx* c) {
   if (c->pool) host_pool_destroy(c->pool);
   c->pool = nullptr;
+  if (c->x_done) (void)hipEventDestroy(c->x_done);
+  c->x_done = nullptr;
   for (void*& h : c->hgrid) {
     if (h) (void)hipHostFree(h);
     h = nullptr;
@@ -657,6 +660,10 @@ lbm_status host_setup(lbm_ctx* c, const std::vector<int>& ids, int threads) {
   build_items(c);
   st = upload_items(c);
   if (st != LBM_OK) return st;
+  if (hipEventCreateWithFlags(&c->x_done, hipEventDisableTiming) != hipSuccess) {
+    c->x_done = nullptr;
+    return fail(LBM_EDEVICE, "hipEventCreate failed");
+  }
   if (threads <= 0) threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
   c->pool = host_pool_create(threads);
   return host_pull(c);
@@ -670,25 +677,14 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// One time step of a heterogeneous run: the GPU sweeps its Blocks while the
-// host threads sweep theirs; then the exchange: host senders packed into the
-// up buffer and unpacked on the GPU, GPU pairs by the copy kernel, GPU
-// senders packed on the GPU and unpacked on the host, host pairs on the host.
-// ev: two events for the GPU sweep time (NULL: untimed).
-lbm_status host_step(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
-  const int from = c->cur, to = 1 - c->cur;
-  const auto t0 = std::chrono::steady_clock::now();
-  if (tm) HIPCHK(hipEventRecord(ev[0], c->stream));
-  enqueue_sweep(c, from, c->stream);
-  if (tm) HIPCHK(hipEventRecord(ev[1], c->stream));
-  host_sweep(c->pool, c->prec, c->f64math, c->hgrid[from], c->hgrid[to], c->hbh.data(), c->host_ids.data(),
-             (int)c->host_ids.size(), c->has_mask ? c->hmask.data() : nullptr, c->geo, c->phd, c->phf);
-  std::chrono::steady_clock::time_point t1;
-  if (tm) {
-    tm->cpu += ms_since(t0);
-    HIPCHK(hipEventSynchronize(ev[1]));
-    t1 = std::chrono::steady_clock::now();
-  }
+// The exchange of a heterogeneous step into grid `to`, first half: host
+// senders packed into the up buffer and host pairs copied on the host; on
+// the stream the up buffer's copy and unpack, the GPU pairs as the schedule
+// says (copy kernel for fused_exchange 0, its rim after the sweep's x faces
+// for 2, nothing after the fully fused sweep), the GPU senders packed and
+// copied to the host.  The sweep's writes into a host Block's device copy
+// are never read.
+lbm_status host_exchange_begin(lbm_ctx* c, int to) {
   host_exchange(c->pool, c->prec, 1, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_hd.data(), (int)c->t_hd.size(),
                 c->h_xup);
   host_exchange(c->pool, c->prec, 0, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_hh.data(), (int)c->t_hh.size(),
@@ -698,9 +694,6 @@ lbm_status host_step(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
     launch_exchange_buf(c->prec, 2, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_hd, (int)c->t_hd.size(), c->d_xup,
                         c->stream);
   }
-  // GPU pairs as the schedule says: the copy kernel (fused_exchange 0), its
-  // rim after the sweep's x faces (2), or nothing after the fused sweep (1);
-  // the sweep's writes into a host Block's device copy are never read
   if (c->sched.fused_exchange == 0)
     launch_exchange(c->prec, c->grid[to], c->d_blocks, c->d_nbr, c->d_t_dd, (int)c->t_dd.size(), c->stream);
   else if (c->sched.fused_exchange == 2)
@@ -711,28 +704,74 @@ lbm_status host_step(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
     HIPCHK(hipMemcpyAsync(c->h_xdn, c->d_xdn, c->xdn_elems * c->sbytes, hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+// Second half, once the down buffer has arrived: GPU senders into the host
+// Blocks' ghost slots.
+void host_exchange_end(lbm_ctx* c, int to) {
   host_exchange(c->pool, c->prec, 2, c->hgrid[to], c->hbh.data(), c->nbh.data(), c->t_dh.data(), (int)c->t_dh.size(),
                 c->h_xdn);
-  if (tm) {
-    float g = 0.f;
-    HIPCHK(hipEventElapsedTime(&g, ev[0], ev[1]));
-    tm->gpu += g;
-    tm->xchg += ms_since(t1);
-    tm->step += ms_since(t0);
-  }
+}
+
+// One time step of a heterogeneous run, its phases timed: the GPU sweeps
+// its Blocks while the host threads sweep theirs; then the exchange.
+// ev: two events for the GPU sweep time.
+lbm_status host_step_timed(lbm_ctx* c, HostTimes* tm, hipEvent_t* ev) {
+  const int from = c->cur, to = 1 - c->cur;
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipEventRecord(ev[0], c->stream));
+  enqueue_sweep(c, from, c->stream);
+  HIPCHK(hipEventRecord(ev[1], c->stream));
+  host_sweep(c->pool, c->prec, c->f64math, c->hgrid[from], c->hgrid[to], c->hbh.data(), c->host_ids.data(),
+             (int)c->host_ids.size(), c->has_mask ? c->hmask.data() : nullptr, c->geo, c->phd, c->phf);
+  tm->cpu += ms_since(t0);
+  HIPCHK(hipEventSynchronize(ev[1]));
+  const auto t1 = std::chrono::steady_clock::now();
+  lbm_status st = host_exchange_begin(c, to);
+  if (st != LBM_OK) return st;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  host_exchange_end(c, to);
+  float g = 0.f;
+  HIPCHK(hipEventElapsedTime(&g, ev[0], ev[1]));
+  tm->gpu += g;
+  tm->xchg += ms_since(t1);
+  tm->step += ms_since(t0);
   c->cur = to;
   c->steps += 1;
   return LBM_OK;
 }
 
+// n heterogeneous steps, pipelined: step k+1's GPU sweep is queued right
+// behind step k's exchange, so the GPU does not wait for the host's
+// unpack; the host unpacks and sweeps step k+1 while the GPU sweeps it.
+lbm_status host_steps_pipelined(lbm_ctx* c, long long n) {
+  if (n <= 0) return LBM_OK;
+  enqueue_sweep(c, c->cur, c->stream);
+  for (long long k = 0; k < n; ++k) {
+    const int from = c->cur, to = 1 - c->cur;
+    host_sweep(c->pool, c->prec, c->f64math, c->hgrid[from], c->hgrid[to], c->hbh.data(), c->host_ids.data(),
+               (int)c->host_ids.size(), c->has_mask ? c->hmask.data() : nullptr, c->geo, c->phd, c->phf);
+    lbm_status st = host_exchange_begin(c, to);
+    if (st != LBM_OK) return st;
+    HIPCHK(hipEventRecord(c->x_done, c->stream));
+    if (k + 1 < n) enqueue_sweep(c, to, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(c->x_done));
+    host_exchange_end(c, to);
+    c->cur = to;
+    c->steps += 1;
+  }
+  return LBM_OK;
+}
+
 lbm_status host_steps(lbm_ctx* c, long long n, HostTimes* tm) {
+  if (!tm) return host_steps_pipelined(c, n);
   hipEvent_t ev[2] = {nullptr, nullptr};
   lbm_status st = LBM_OK;
-  if (tm)
-    for (hipEvent_t& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) st = fail(LBM_EDEVICE, "hipEventCreate failed");
-  for (long long k = 0; k < n && st == LBM_OK; ++k) st = host_step(c, tm, ev);
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) st = fail(LBM_EDEVICE, "hipEventCreate failed");
+  for (long long k = 0; k < n && st == LBM_OK; ++k) st = host_step_timed(c, tm, ev);
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   return st;

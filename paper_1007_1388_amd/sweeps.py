@@ -30,7 +30,8 @@ hbm:    read-only, write-only and copy streams over 2 GiB buffers (well past
 hetero: the porous 512x256x256 channel in its uneven Blocks, FP32 (Sec. 5.3's
         heterogeneous study on one node): the GPU alone, then the last k
         Blocks on the host CPU (k = 1, 2, 4, 8, 16, 16 threads) with the GPU
-        sweep, host sweep, exchange and whole-step times; the host sweep's
+        sweep, host sweep, exchange and whole-step times of phase-timed steps
+        and the step time of lbm_step's pipelined steps; the host sweep's
         rate against its thread count on the last Block; and the static load
         balance (lbm_balance_host_blocks).
 open:   a 512x256x256 duct (y periodic, z walls), FP32: x periodic with a
@@ -174,10 +175,17 @@ def hetero_sweep(steps, threads=16):
         lat.set_host_blocks(ids, threads=threads)
         lat.step(2)
         g, c, x, s = lat.step_host_timed(steps)
+        # the same split stepped as lbm_step runs it (the next GPU sweep
+        # queued behind the exchange)
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        sp = (time.perf_counter() - t0) * 1e3 / steps
         fh = _fluid(solid, blocks[nb - k:])
         print(json.dumps(dict(study="hetero", case="split", threads=threads, host_blocks=k, host_fluid=fh,
                               gpu_sweep_ms=round(g, 4), cpu_sweep_ms=round(c, 4), exchange_ms=round(x, 4),
-                              step_ms=round(s, 4), mlups=round(nf / s / 1e3, 1))), flush=True)
+                              step_ms=round(s, 4), pipelined_step_ms=round(sp, 4),
+                              mlups=round(nf / sp / 1e3, 1))), flush=True)
     lat.set_host_blocks([])
     k, tg, th = lat.balance_host_blocks(threads=threads, trial_steps=steps)
     print(json.dumps(dict(study="hetero", case="balance", threads=threads, host_blocks=k, gpu_alone_ms=round(tg, 4),

@@ -23,23 +23,27 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
+    """Hash of the sources that decide what the sweep moves through HBM: the
+    kernels, the data layout, and the runtime (work-item order and launch
+    shapes)."""
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+    for f in ("lbm_kernels.hip", "lbm_internal.h", "lbm_runtime.hip"):
         with open(os.path.join(ROOT, "paper_1007_1388_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name, src_hash):
+def traffic_from_profile(name, src_hash, seed=0):
     """HBM bytes per sweep launch from committed rocprofv3 counter summaries,
-    or None when absent or taken on a different kernel source."""
+    or None when absent, taken on a different kernel source or on another
+    seed of the workload."""
     path = os.path.join(PROFILE_DIR, name)
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != src_hash:
+    if d.get("kernel_hash") != src_hash or d.get("seed", 0) != seed:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -199,7 +203,8 @@ def main():
     # algorithmic bytes of one sweep launch over its measured mean duration
     achieved = nf * bpu / (r["sweep_ms"] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    tr = traffic_from_profile("sweep_%s_%s_pmc.json" % (prec, args.workload), src_hash)
+    tr = traffic_from_profile("sweep_%s_%s_pmc.json" % (prec, args.workload), src_hash,
+                              args.seed if solid is not None else 0)
     if prec == "f64" or (prec == "f32" and f64m):
         arith = "f64"
     elif prec == "f32":

@@ -272,6 +272,44 @@ int slot_of(const std::vector<int>& cuts, int v) {
 
 int cells_per_lane(const lbm_ctx* c, const lbm_schedule& s);
 
+// XCD-aware item order for many Blocks.  Workgroup w of a launch runs on
+// XCD w % 8 (the dispatcher deals workgroups to the 8 XCDs in turn, each
+// with its own L2), and the sweep gives item w to workgroup w (or w + k *
+// grid with a persistent grid, a multiple of 8).  The sweep reads rows of
+// the planes next to its own (pulls along z, the own-cell loads across
+// obstacle links, ghost rows), which stay in an L2 only if the neighbouring
+// planes' items run on the same XCD close in time.  So whole Blocks are
+// dealt to 8 queues (largest first, to the shortest queue), each queue keeps
+// its Blocks' items plane by plane, and the list interleaves the queues:
+// item 8 s + x is the s-th of queue x.  Queues differ by at most one Block's
+// items; past the shortest, the tail keeps the interleave of the rest.  With
+// few Blocks (one Block walks its planes in order on all XCDs alike) the
+// order is left as built.
+void order_items_by_xcd(lbm_ctx* c) {
+  constexpr int X = 8;
+  const int nb = (int)c->bh.size();
+  if (nb < 2 * X) return;
+  std::vector<std::vector<ItemDev>> per_block(nb);
+  for (const ItemDev& it : c->items_h) per_block[it.block].push_back(it);
+  std::vector<int> order(nb);
+  for (int j = 0; j < nb; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int u, int v) { return per_block[u].size() > per_block[v].size(); });
+  std::vector<std::vector<ItemDev>> q(X);
+  for (int j : order) {
+    int best = 0;
+    for (int x = 1; x < X; ++x)
+      if (q[x].size() < q[best].size()) best = x;
+    q[best].insert(q[best].end(), per_block[j].begin(), per_block[j].end());
+  }
+  c->items_h.clear();
+  size_t longest = 0;
+  for (const auto& v : q) longest = std::max(longest, v.size());
+  for (size_t k = 0; k < longest; ++k)
+    for (int x = 0; x < X; ++x)
+      if (k < q[x].size()) c->items_h.push_back(q[x][k]);
+}
+
 void build_items(lbm_ctx* c) {
   c->items_h.clear();
   const int target = std::max(1, c->sched.item_cells);
@@ -300,6 +338,7 @@ void build_items(lbm_ctx* c) {
     for (int z = 0; z < cz; ++z)
       for (int y = 0; y < b; y += rows) c->items_h.push_back({j, z, y, std::min(rows, b - y)});
   }
+  order_items_by_xcd(c);
   // the GPU sweep of a heterogeneous run covers the GPU Blocks only
   c->sweep_items_h.clear();
   if (hetero(c))

@@ -16,7 +16,7 @@ blocks: the 384^3 periodic cube as 1, 8, 27, 64 and 216 equal Blocks, and
         three exchange schedules (0 copy kernel, 2 x faces written by the
         sweep, 1 fully fused), for the porous channel in its uneven Blocks and
         for 64 uneven Blocks (4x4x4, edges from {32, 48, 64}): the cost of
-        Blocks and of their on-GPU copies, Sec. 5.2.
+        Blocks and of their on-GPU copies, Sec. 5.1.
 pad:    single-Block periodic cubes of odd and even edge around 64, 70,
         128 and 256 (the paper's odd-size effects, Sec. 5.1) with rows
         aligned to 128-byte lines and no extra padding (row_pad -1) or one

@@ -115,6 +115,38 @@ def copy_probe(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+# copy-type patterns of lbm_hbm_probe whose best rate is the ceiling the
+# sweep (every stored value read once and written once) is read against:
+# (kind, unroll, nontemporal, grid)
+CEILING_PROBES = [(2, u, 1, g) for u in (1, 2) for g in (256, 512, 1024, 4096)] + \
+                 [(3, u, 1, g) for u in (4, 8) for g in (1024, 8192, 16384)] + \
+                 [(5, u, 1, g) for u in (1, 2, 4) for g in (256, 512, 1024, 4096)] + [(6, 1, 1, 0)]
+
+
+def copy_ceiling(nbytes=2 << 30, reps=4):
+    """Best copy-type bandwidth (GB/s, read + write) over CEILING_PROBES on
+    `nbytes` buffers, and the pattern that reached it."""
+    import torch
+    from paper_1007_1388_amd import lbm
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream().cuda_stream
+    best = (0.0, None)
+    for kind, unroll, nt, grid in CEILING_PROBES:
+        ms = lbm.lbm_hbm_probe(kind, unroll, nt, a.data_ptr(), b.data_ptr(), nbytes, grid, reps, st)
+        moved = 2 * nbytes
+        if kind == 5:
+            per = nbytes // 19 // 4096 * 4096
+            while 19 * per + 18 * 768 > nbytes:
+                per -= 4096
+            moved = 2 * 19 * per
+        gbs = moved / (ms * 1e-3) / 1e9
+        if gbs > best[0]:
+            best = (gbs, dict(kind=kind, unroll=unroll, nontemporal=nt, grid=grid))
+    del a, b
+    return best
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -156,6 +188,64 @@ def cpu_baseline(p, solid, seconds=12.0, single_steps=3):
                 single_thread_value=round(cells * single_steps / dt1 / 1e6, 3), cpu_model=cpu_model())
 
 
+def porous_leg(seed=0, steps=1000, warmup=100):
+    """The porous channel 512x256x256 in its seeded uneven Blocks with
+    spheres (FP32 storage): MLUPS and the sweep's roofline fraction."""
+    p, blocks, solid = workload("porous512", seed)
+    r = time_gpu(p, blocks, solid, "f32", False, steps, warmup, {"graph_steps": 10}, None, repeats=1)
+    info = r["info"]
+    nf = info["n_fluid"]
+    achieved = nf * info["bytes_per_update"] / (r["sweep_ms"] * 1e-3) / 1e9
+    tr = traffic_from_profile("sweep_f32_porous512_pmc.json", kernel_source_hash(), seed)
+    return {"workload": "porous512 512x256x256, seed %d, %d uneven Blocks, solid fraction %.4f"
+                        % (seed, info["n_blocks"], float(solid.mean())),
+            "value": round(nf * steps / r["wall"] / 1e6, 1), "unit": "MLUPS", "steps": steps,
+            "ms_per_step": round(r["wall"] * 1e3 / steps, 5), "kernel_ms": round(r["sweep_ms"], 5),
+            "exchange_ms": round(r["exchange_ms"], 5), "bytes_per_update": info["bytes_per_update"],
+            "achieved_gbs": round(achieved, 1), "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic_gbs": (round(tr / (r["sweep_ms"] * 1e-3) / 1e9, 1) if tr else None),
+            "schedule": r["schedule"]}
+
+
+def precision_leg(n=384, steps=5000, tau=0.55, lid=0.1):
+    """The n^3 lid-driven cavity in FP64, FP32, shifted FP16 and shifted BF16
+    storage for `steps` steps: MLUPS, the 16-bit speedup over FP32, and the
+    normwise velocity error of each run against the FP64 run."""
+    import numpy as np
+    import torch
+    from paper_1007_1388_amd import lbm
+    out, ref = {}, None
+    for prec in ("f64", "f32", "f16s", "bf16s"):
+        lat = lbm.Lattice((n, n, n), walls=(True, True, True), wall_u={"+z": (lid, 0, 0)}, tau=tau,
+                          precision=prec)
+        lat.set_schedule(graph_steps=10)
+        lat.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps - 10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, u = lat.macroscopic()
+        sweep_ms, _ = lat.step_timed(20)
+        info = lat.info()
+        lat.close()
+        achieved = n ** 3 * info["bytes_per_update"] / (sweep_ms * 1e-3) / 1e9
+        row = {"value": round(n ** 3 * (steps - 10) / dt / 1e6, 1), "kernel_ms": round(sweep_ms, 5),
+               "bytes_per_update": info["bytes_per_update"], "roofline_frac": round(achieved / HBM_PEAK_GBS, 4)}
+        if prec == "f64":
+            ref = u
+        else:
+            d = u - ref
+            row["err_vs_f64_inf"] = float(np.abs(d).max() / np.abs(ref).max())
+            row["err_vs_f64_l2"] = float(np.sqrt((d ** 2).sum() / (ref ** 2).sum()))
+        out[prec] = row
+        del u
+    for prec in ("f16s", "bf16s"):
+        out[prec]["speedup_vs_f32"] = round(out[prec]["value"] / out["f32"]["value"], 3)
+    return {"workload": "cavity384 %d^3 lid-driven cavity, tau %g, lid %g, %d steps" % (n, tau, lid, steps),
+            "unit": "MLUPS", "storage": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +264,8 @@ def main():
                     help="ghost exchange: 0 copy kernel, 1 fused into the sweep, 2 x faces by the sweep and "
                          "the rest by the copy kernel (default: the library's, 0 for one Block, 2 for several)")
     ap.add_argument("--autotune", default=None, help="autotune cache file (runs the schedule autotuner)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the porous-channel and storage-precision legs of the default workload")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run the copy probe on this many bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -188,6 +280,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_only, "copy_gbs": round(gbs, 1)}), flush=True)
         return
     copy_gbs = copy_probe()
+    ceil_gbs, ceil_pattern = copy_ceiling()
     p, blocks, solid = workload(args.workload, args.seed)
     prec = args.precision
     f64m = bool(args.fp64_math) and prec in ("f32", "f64")
@@ -239,7 +332,8 @@ def main():
                      "kernel": "k_sweep", "kernel_ms": round(r["sweep_ms"], 5),
                      "exchange_ms": round(r["exchange_ms"], 5), "step_ms_events": round(r["step_ms"], 5),
                      "bytes_per_update": bpu, "copy_probe_gbs": round(copy_gbs, 1),
-                     "frac_of_copy": round(achieved / copy_gbs, 4), "kernel_hash": src_hash},
+                     "copy_ceiling_gbs": round(ceil_gbs, 1), "copy_ceiling_pattern": ceil_pattern,
+                     "frac_of_copy": round(achieved / ceil_gbs, 4), "kernel_hash": src_hash},
     }
     if not args.no_f64 and prec == "f32":
         n64 = max(1, args.steps // 2)
@@ -250,6 +344,9 @@ def main():
         out["f64_storage"] = {"value": round(m64, 1), "unit": "MLUPS", "steps": n64,
                               "roofline_frac": round(a64 / HBM_PEAK_GBS, 4), "achieved_gbs": round(a64, 1),
                               "kernel_ms": round(r64["sweep_ms"], 5)}
+    if not args.no_legs and args.workload == "poiseuille256" and prec == "f32":
+        out["porous512"] = porous_leg(seed=0)
+        out["cavity384_precision"] = precision_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, solid)
     print(json.dumps(out), flush=True)

@@ -223,8 +223,11 @@ lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s);
 /* Time candidate schedules for `trial_steps` steps each on this context and
  * apply the fastest.  The state is saved before and restored after, so the
  * simulation is unchanged.  cache_path (may be NULL) names a text file of
- * earlier choices keyed by the problem signature; a hit skips the trials.
- * The chosen schedule is written to *chosen when non-NULL. */
+ * earlier choices keyed by the problem signature (device, storage and
+ * arithmetic precision, obstacles, dimensions, the Block tiling, the six face
+ * kinds and row_pad); a hit skips the trials, a line this context refuses is
+ * skipped, and a new choice is appended.  The chosen schedule is written to
+ * *chosen when non-NULL; the schedule's graph_steps is kept. */
 lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
                         lbm_schedule* chosen);
 
@@ -289,15 +292,26 @@ lbm_status lbm_bw_probe(void* dst, const void* src, size_t bytes, int32_t reps, 
                         double* ms_per_copy);
 
 /* HBM bandwidth ceilings of plain access patterns (the patterns the sweep's
- * bandwidth is read against; Sec. 3.1's attainable-bandwidth benchmark for
- * three patterns): kind 0 reads `a`, 1 writes `b`, 2 copies a -> b, over
- * `bytes` (a multiple of 16, device buffers of that size; b is overwritten,
- * a is only read) in 16-byte accesses, `unroll` (1, 2, 4 or 8) independent
- * accesses in flight per thread, nontemporal = 1 for streaming loads and
- * stores, `grid` workgroups of 256 threads (0: 16 per compute unit).  After
- * one warm-up pass, reps passes on `stream`; *ms = mean time per pass.
- * LBM_EINVAL on bad arguments (a may be NULL for kind 1), LBM_EDEVICE on a
- * HIP error.  Synchronises. */
+ * bandwidth is read against; Sec. 3.1's attainable-bandwidth benchmark
+ * widened to several patterns).  kind:
+ *   0 reads `a`; 1 writes `b`; 2 copies a -> b, grid-strided 16-byte accesses;
+ *   3 copies a -> b in one contiguous chunk per workgroup;
+ *   4 triad b = a0 + 3 a1 (a holds a0 then a1: 2 * bytes);
+ *   5 the sweep's pattern without arithmetic: `bytes` per side cut into 19
+ *     arrays (starts staggered by 768 bytes), every lane reads one word of
+ *     all 19 arrays of a and writes them to the 19 arrays of b; the word is
+ *     4 * unroll bytes (unroll 1, 2 or 4); needs bytes >= 19 * 8192;
+ *   6 hipMemcpyAsync device to device (a -> b); 7 hipMemsetD32Async of b.
+ * Bytes moved per pass: `bytes` for kinds 0, 1 and 7, 3 * bytes for kind 4,
+ * 2 * bytes for the copies (kind 5: 2 * 19 * P, P the largest multiple of 4096
+ * with 19 P + 13824 <= bytes).
+ * Buffers are device buffers of that size (b is overwritten, a is only
+ * read), `unroll` (1, 2, 4 or 8) independent accesses in flight per thread,
+ * nontemporal = 1 for streaming loads and stores, `grid` workgroups of 256
+ * threads (0: 16 per compute unit; ignored by kinds 6 and 7).  After one
+ * warm-up pass, reps passes on `stream`; *ms = mean time per pass.
+ * LBM_EINVAL on bad arguments (a may be NULL for kinds 1 and 7),
+ * LBM_EDEVICE on a HIP error.  Synchronises. */
 lbm_status lbm_hbm_probe(int32_t kind, int32_t unroll, int32_t nontemporal, const void* a, void* b,
                          size_t bytes, int32_t grid, int32_t reps, void* stream, double* ms);
 

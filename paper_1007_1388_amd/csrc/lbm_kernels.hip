@@ -20,6 +20,8 @@
 // bit-identical), so fused multiply-adds are written out where wanted.
 #pragma clang fp contract(off)
 
+
+
 namespace lbm {
 
 // ------------------------------------------------------------------ lattice
@@ -142,6 +144,44 @@ __device__ __forceinline__ void buf_store(T* base, uint32_t boff, T v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rs, boff, 0, 0);
 }
 
+// Addressing of the one-cell-per-lane sweep.  The 19 population arrays of a
+// Block are covered by five buffer resources, one per group of arrays
+// {0..4}, {5..8}, {9..12}, {13..16}, {17, 18} (a direction and its opposite
+// share a group), each based two elements before its first array.  A
+// pulled or stored value is then (resource, the lane's 32-bit offset, a
+// 32-bit scalar offset of the direction's row, an immediate), so the 38
+// streams of a row cost no per-direction 64-bit address arithmetic and the
+// rows of an item share the lane offset.  Group offsets stay below
+// 6 Sf elements (checked when the Block is created).
+__host__ __device__ constexpr int GRP0(int i) { return i < 5 ? 0 : (i < 9 ? 5 : (i < 13 ? 9 : (i < 17 ? 13 : 17))); }
+constexpr int kGroups = 5;
+__host__ __device__ constexpr int GRPI(int i) { return i < 5 ? 0 : (i < 9 ? 1 : (i < 13 ? 2 : (i < 17 ? 3 : 4))); }
+constexpr uint32_t kRange = 0xFFFFFFF0u;  // records of a group resource; an offset of kRange reads zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grp_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)kRange, 0x00020000);
+}
+template <typename T, bool NT>
+__device__ __forceinline__ T rs_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  constexpr int aux = NT ? 2 : 0;  // streaming (nt)
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, aux));
+  else if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, aux));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, aux));
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void rs_store(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T v) {
+  constexpr int aux = NT ? 2 : 0;
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(unsigned int __attribute__((__vector_size__(8))), v),
+                                          rs, voff, soff, aux);
+  else if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff, aux);
+  else
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rs, voff, soff, aux);
+}
+
 // VEC values loaded into whole 32-bit registers (a lone 16-bit value is
 // zero-extended) and split later.
 template <int BYTES> struct WideRaw { typedef typename Raw<BYTES>::V V; };
@@ -175,6 +215,50 @@ __device__ __forceinline__ T sh_down(T v) {  // value of lane + 1
   else return __shfl_down(v, 1, 64);
 }
 
+// A wave-uniform value moved into scalar registers behind an opaque point:
+// what is computed from it stays after that point.
+__device__ __forceinline__ int sgpr_launder(int v) {
+  int r = __builtin_amdgcn_readfirstlane(v);
+  asm volatile("" : "+s"(r));
+  return r;
+}
+__device__ __forceinline__ long long sgpr_launder(long long v) {
+  int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+  int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Kernel arguments of the sweep read through the kernel-argument segment
+// (address space 4: scalar loads): the SweepArgs first, the Phys<C> next at
+// its natural alignment (the order and alignment of explicit kernel
+// arguments).
+#define KAS __attribute__((address_space(4)))
+template <bool VIA_SEGMENT, typename C> struct ArgPtrs;
+template <typename C>
+struct ArgPtrs<true, C> {
+  const SweepArgs KAS* a;
+  const Phys<C> KAS* p;
+  __device__ __forceinline__ static ArgPtrs at(const char KAS* k) {
+    asm volatile("" : "+s"(k));
+    constexpr size_t off = (sizeof(SweepArgs) + alignof(Phys<C>) - 1) / alignof(Phys<C>) * alignof(Phys<C>);
+    return ArgPtrs{(const SweepArgs KAS*)k, (const Phys<C> KAS*)(k + off)};
+  }
+  __device__ __forceinline__ static ArgPtrs get(const SweepArgs&, const Phys<C>&) {
+    return at((const char KAS*)__builtin_amdgcn_kernarg_segment_ptr());
+  }
+  __device__ __forceinline__ ArgPtrs again() const { return at((const char KAS*)a); }
+};
+// the plain form: the parameters themselves (the compiler keeps what it
+// likes in registers)
+template <typename C>
+struct ArgPtrs<false, C> {
+  const SweepArgs* a;
+  const Phys<C>* p;
+  __device__ __forceinline__ static ArgPtrs get(const SweepArgs& A, const Phys<C>& ph) { return ArgPtrs{&A, &ph}; }
+  __device__ __forceinline__ ArgPtrs again() const { return *this; }
+};
+
 // Flags of the wall faces that the sources of a lane's cells lie beyond.
 struct WallFlags {
   bool lox, hix, loy, hiy, loz, hiz;
@@ -198,8 +282,8 @@ __device__ __forceinline__ bool wall_link(const WallFlags& w, int i, int k) {
 // 6 w_i rho0 (e_i . u_w) of the first moving face (order -x,+x,-y,+y,-z,+z)
 // that the source of a wall link lies beyond (the half-way bounce-back rule
 // with wall velocity, Sec. 2.1).
-template <typename C, int VEC>
-__device__ __forceinline__ C wall_corr(const SweepArgs& A, const Phys<C>& ph, const WallFlags& w, int i, int k) {
+template <typename C, int VEC, typename AT, typename PT>
+__device__ __forceinline__ C wall_corr(const AT& A, const PT& ph, const WallFlags& w, int i, int k) {
   const int ex = EXd(i), ey = EYd(i), ez = EZd(i);
   C cw = (C)0;
   if (ez > 0 && w.loz && A.geo.moving[4]) cw = ph.corr[i][4];
@@ -254,11 +338,40 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
-__device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph, const BlockDev& B, int bid,
+__device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& ph_in, const BlockDev& B_in, int bid,
                                           int z, int y0w, int seg, int yend, int xw, const GhostTgt* gts) {
+  // The kernel's arguments (this sweep's pointers, the geometry and the
+  // physical constants) are read through the kernel-argument segment at the
+  // point of use, here and again after the pull phase, instead of being
+  // kept in scalar registers across the item and row loops (which spills
+  // them into vector lanes): the pointer is laundered so that no load is
+  // hoisted above these points.
+  // Which of these help was measured per kernel variant on gfx950 (same
+  // box, A/B): reading the arguments at the point of use pays for every
+  // variant but the 16-bit ones without obstacles; laundering the Block's
+  // layout values, for FP32 and FP64 storage without obstacles; the
+  // scalar-offset buffer addressing below, for the obstacle variants (the
+  // porous channel's sweep 1.165 -> 1.108 ms; the others lose 1-2 % with it).
+  constexpr bool KARGS = !(PREC >= 2 && !MASK);
+  constexpr bool BLAUNDER = !MASK && PREC <= 1;
+  constexpr bool ADDR = MASK && VEC == 1;
+  auto ka = ArgPtrs<KARGS, C>::get(A_in, ph_in);
+  auto pa = ka.a;
+  auto pp = ka.p;
+  // The Block's layout values, laundered likewise: what the row's addresses
+  // derive from them is computed per row, not kept for the whole item.
+  BlockDev B = B_in;
+  if constexpr (BLAUNDER) {
+    B.base = sgpr_launder(B.base);
+    B.Sf = sgpr_launder(B.Sf);
+    B.Sz = sgpr_launder(B.Sz);
+    B.xgo = sgpr_launder(B.xgo);
+    B.Sx = sgpr_launder(B.Sx);
+    B.Ry = sgpr_launder(B.Ry);
+  }
   using T = typename Stor<PREC>::T;
-  const T* __restrict__ src = (const T*)A.src;
-  T* __restrict__ dst = (T*)A.dst;
+  const T* __restrict__ src = (const T*)pa->src;
+  T* __restrict__ dst = (T*)pa->dst;
   const int lane = threadIdx.x & 63;
   const int a = B.dim[0], b = B.dim[1], c = B.dim[2];
   const int r = lane / xw;
@@ -269,6 +382,17 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // neighbour lane of its own live row.
   if (x0 >= a || y >= yend) return;
 
+  // The group resources and scalar row offsets of the one-cell-per-lane
+  // addressing are rebuilt for every row from the Block's base and strides
+  // (laundered here so that the compiler does not keep ten resources and
+  // some forty offsets of an item live across its rows, which spills scalar
+  // registers into vector lanes).
+  long long gsrc = (long long)(uintptr_t)pa->src, gdst = (long long)(uintptr_t)pa->dst, gbase = B.base;
+  if constexpr (VEC == 1 && BLAUNDER) {
+    asm volatile("" : "+s"(gsrc), "+s"(gdst), "+s"(gbase));
+  }
+  const T* gsp = (const T*)(uintptr_t)gsrc;
+  T* gdp = (T*)(uintptr_t)gdst;
   // Scalar bases address row starts; the lane offset carries the row within
   // the wave, the segment and the lane's cells (all non-negative).
   const long long rb = B.base + (long long)(z + 1) * B.Sz + (long long)(y0w + 1) * B.Sx;
@@ -296,9 +420,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     solid[k] = false;
   }
   if constexpr (MASK) {
-    const uint32_t* mp = A.mask + B.mask + ((long long)z * b + y) * a + x0;
+    const uint32_t* mp = pa->mask + B.mask + ((long long)z * b + y) * a + x0;
 #pragma unroll
     for (int k = 0; k < VEC; ++k) m[k] = mp[k];
+    if constexpr (VEC == 1) solid[0] = (m[0] & kSolidBit) != 0;
     __builtin_amdgcn_sched_barrier(0);
   }
 
@@ -320,7 +445,33 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     const uint32_t xgb = (uint32_t)((dxg + r) * (long long)sizeof(T));
     const uint32_t xlo = wx ? xwrap_lo : xgb, xhi = wx ? xwrap_hi : xgb;
     const uint32_t S1 = (uint32_t)sizeof(T);
-    if constexpr (VEC == 1) {
+    if constexpr (VEC == 1 && ADDR) {
+      // group resource of direction i; scalar offset of its source row;
+      // the lane offset (lob + s, shared by all directions) plus (1 - e_x) s
+      const int g0 = GRP0(i);
+      const __amdgpu_buffer_rsrc_t rs = grp_rsrc(gsp + (gbase + (long long)g0 * B.Sf - 2));
+      const uint32_t so = (uint32_t)(((long long)(i - g0) * B.Sf + (long long)(zs + 1) * B.Sz +
+                                      (long long)(ys + 1) * B.Sx) * (long long)sizeof(T));
+      uint32_t vo = lob + (uint32_t)((2 - ex) * (int)sizeof(T));
+      if (ex != 0) {
+        // x-ghost slot of the source row (or, wrapping in x, the other end
+        // of the row), as a lane offset against the same scalar offset
+        const long long xg = B.xgo + (long long)(zs + 1) * (B.Ry - B.Sz) + (long long)(ys + 1) * (1 - B.Sx) + 2;
+        const uint32_t xgv = (uint32_t)((xg + r) * (long long)sizeof(T));
+        const uint32_t xwv = (uint32_t)((ex > 0 ? r * B.Sx + a + 1 : r * B.Sx + 2) * (int)sizeof(T));
+        const uint32_t xv = wx ? xwv : xgv;
+        if (ex > 0) vo = xg_lo ? xv : vo;
+        if (ex < 0) vo = xg_hi ? xv : vo;
+      }
+      // one load per value: a lane with an obstacle link along e_i reads its
+      // own slot of array ibar (same group) instead of the solid source, a
+      // solid lane reads nothing (offset past the range)
+      const uint32_t own = (uint32_t)(((long long)(OPPd(i) - g0) * B.Sf + (long long)(z + 1) * B.Sz +
+                                       (long long)(y0w + 1) * B.Sx) * (long long)sizeof(T)) + lob + 2u * S1;
+      uint32_t o = (i != 0 && ((m[0] >> i) & 1u)) ? own : so + vo;
+      o = solid[0] ? kRange : o;
+      W[i][0] = rs_load<T, NT>(rs, o, 0u);
+    } else if constexpr (VEC == 1) {
       uint32_t off = lob + (uint32_t)((1 - ex) * (int)sizeof(T));
       if (ex > 0) off = xg_lo ? xlo : off;
       if (ex < 0) off = xg_hi ? xhi : off;
@@ -367,7 +518,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     }
   }
 
-  if constexpr (MASK) {
+  if constexpr (MASK && VEC > 1) {
     // Half-way bounce-back at obstacles on the pull side: when x - e_i is
     // solid, cell x receives its own f*_ibar of the previous step, read from
     // its own slot of array ibar (one more load, only for directions where
@@ -397,16 +548,19 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   }
 
   // ---- update phase
+  ka = ka.again();
+  pa = ka.a;
+  pp = ka.p;
   const int gx0 = B.org[0] + x0, gy = B.org[1] + y, gz = B.org[2] + z;
   WallFlags wf;
-  wf.lox = A.geo.fwall[0] && gx0 == 0;
-  wf.hix = A.geo.fwall[1] && gx0 + VEC - 1 == A.geo.n[0] - 1;
-  wf.loy = A.geo.fwall[2] && gy == 0;
-  wf.hiy = A.geo.fwall[3] && gy == A.geo.n[1] - 1;
-  wf.loz = A.geo.fwall[4] && gz == 0;
-  wf.hiz = A.geo.fwall[5] && gz == A.geo.n[2] - 1;
-  const bool moving = A.geo.moving[0] | A.geo.moving[1] | A.geo.moving[2] | A.geo.moving[3] | A.geo.moving[4] |
-                      A.geo.moving[5];
+  wf.lox = pa->geo.fwall[0] && gx0 == 0;
+  wf.hix = pa->geo.fwall[1] && gx0 + VEC - 1 == pa->geo.n[0] - 1;
+  wf.loy = pa->geo.fwall[2] && gy == 0;
+  wf.hiy = pa->geo.fwall[3] && gy == pa->geo.n[1] - 1;
+  wf.loz = pa->geo.fwall[4] && gz == 0;
+  wf.hiz = pa->geo.fwall[5] && gz == pa->geo.n[2] - 1;
+  const bool moving = pa->geo.moving[0] | pa->geo.moving[1] | pa->geo.moving[2] | pa->geo.moving[3] | pa->geo.moving[4] |
+                      pa->geo.moving[5];
 
   // moments (Sec. 2.1): drho = sum f~, rho0 u = sum e f~, plus half force.
   // FP32 storage with FP32 arithmetic (HYB) keeps the velocity in FP64: the
@@ -431,19 +585,19 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
     }
     drho[k] = d;
     if constexpr (HYB) {
-      dux[k] = fma((double)jx, ph.dinv_rho0, ph.dhg[0]);
-      duy[k] = fma((double)jy, ph.dinv_rho0, ph.dhg[1]);
-      duz[k] = fma((double)jz, ph.dinv_rho0, ph.dhg[2]);
+      dux[k] = fma((double)jx, pp->dinv_rho0, pp->dhg[0]);
+      duy[k] = fma((double)jy, pp->dinv_rho0, pp->dhg[1]);
+      duz[k] = fma((double)jz, pp->dinv_rho0, pp->dhg[2]);
       ux[k] = (C)dux[k];
       uy[k] = (C)duy[k];
       uz[k] = (C)duz[k];
     } else {
-      ux[k] = fma(jx, ph.inv_rho0, ph.hg[0]);
-      uy[k] = fma(jy, ph.inv_rho0, ph.hg[1]);
-      uz[k] = fma(jz, ph.inv_rho0, ph.hg[2]);
+      ux[k] = fma(jx, pp->inv_rho0, pp->hg[0]);
+      uy[k] = fma(jy, pp->inv_rho0, pp->hg[1]);
+      uz[k] = fma(jz, pp->inv_rho0, pp->hg[2]);
     }
     uu15[k] = (C)1.5 * fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
-    ug3[k] = ph.rho0x3 * fma(ux[k], ph.g[0], fma(uy[k], ph.g[1], uz[k] * ph.g[2]));
+    ug3[k] = pp->rho0x3 * fma(ux[k], pp->g[0], fma(uy[k], pp->g[1], uz[k] * pp->g[2]));
   }
 
   // stores of direction i; solid cells store zero (no cell reads their
@@ -451,6 +605,17 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // cache line whole (partial-line writes cost the memory a
   // read-modify-write)
   auto store_dir = [&](int i, const T (&o)[VEC]) {
+    if constexpr (VEC == 1 && ADDR) {
+      // group resource of direction i, scalar offset of the cell's row
+      const int g0 = GRP0(i);
+      const __amdgpu_buffer_rsrc_t rs = grp_rsrc(gdp + (gbase + (long long)g0 * B.Sf - 2));
+      const uint32_t so = (uint32_t)(((long long)(i - g0) * B.Sf + (long long)(z + 1) * B.Sz +
+                                      (long long)(y0w + 1) * B.Sx) * (long long)sizeof(T));
+      T v = o[0];
+      if constexpr (MASK) v = solid[0] ? from_c<PREC, double>(0.0) : v;
+      rs_store<T, NT>(rs, lob + 2u * (uint32_t)sizeof(T), so, v);
+      return;
+    }
     T* base = dst + (rb + (long long)i * B.Sf);
     if constexpr (MASK) {
       T v[VEC];
@@ -476,7 +641,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
       if (bb) {
         T v = o[k];
         if (moving && wall_link<VEC>(wf, qb, k))
-          v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(A, ph, wf, qb, k));
+          v = from_c<PREC, C>(to_c<PREC, C>(o[k]) + wall_corr<C, VEC>(*pa, *pp, wf, qb, k));
         // shifted row of array qbar (wrapped like the pull that reads it),
         // one element early so that the lane offset stays non-negative
         const int zt = wz ? wrapc(z + ezq, c) : z + ezq;
@@ -523,8 +688,8 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // kernel copies the rim rows)
   const bool xsend = FX == 1 ? !yz_face : FX == 2;
   if (xsend) {
-    const GhostTgt& Gm = A.ghost[bid * 27 + 12];
-    const GhostTgt& Gp = A.ghost[bid * 27 + 14];
+    const GhostTgt& Gm = pa->ghost[bid * 27 + 12];
+    const GhostTgt& Gp = pa->ghost[bid * 27 + 14];
     xm_on = Gm.kind != 0;
     xp_on = Gp.kind != 0;
     xm0 = Gm.xg0 + (long long)z * Gm.Ry + y0w;
@@ -543,13 +708,13 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
   // at most one face cell.
   double* sp = nullptr;
   int sdir = 0;  // e_x of the populations that enter through the lane's face
-  if (OPEN && A.side != nullptr) {
-    const long long cell = (long long)gz * A.geo.n[1] + gy;
-    if (A.geo.open[0] && gx0 == 0) {
-      sp = A.side + 16 * cell;
+  if (OPEN && pa->side != nullptr) {
+    const long long cell = (long long)gz * pa->geo.n[1] + gy;
+    if (pa->geo.open[0] && gx0 == 0) {
+      sp = pa->side + 16 * cell;
       sdir = 1;
-    } else if (A.geo.open[1] && gx0 + VEC - 1 == A.geo.n[0] - 1) {
-      sp = A.side + 16 * ((long long)A.geo.n[1] * A.geo.n[2] + cell);
+    } else if (pa->geo.open[1] && gx0 + VEC - 1 == pa->geo.n[0] - 1) {
+      sp = pa->side + 16 * ((long long)pa->geo.n[1] * pa->geo.n[2] + cell);
       sdir = -1;
     }
   }
@@ -590,13 +755,13 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
       // rest: feq~_0 = w0 (drho + rho0 (-1.5 u.u)), F_0 = w0 rho0 (-3 u.g)
-      const C feq = ph.w[0] * fma(ph.rho0, -uu15[k], drho[k]);
-      const C F = -ph.w[0] * ug3[k];
-      const C even = fma(ph.omega, feq, ph.fcoef * F);
+      const C feq = pp->w[0] * fma(pp->rho0, -uu15[k], drho[k]);
+      const C F = -pp->w[0] * ug3[k];
+      const C even = fma(pp->omega, feq, pp->fcoef * F);
       if constexpr (HYB)
-        o[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[0][k]), (double)even));
+        o[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[0][k]), (double)even));
       else
-        o[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[0][k]), even));
+        o[k] = from_c<PREC, C>(fma(pp->omc, to_c<PREC, C>(W[0][k]), even));
     }
     store_dir(0, o);
   }
@@ -624,18 +789,18 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A, const Phys<C>& ph,
         if (EZd(i) < 0) eu -= uz[k];
       }
       // even part (shared by i and its opposite) and odd part (flips sign)
-      const C sym = ph.w[WCLS(i)] * fma(ph.rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
-      const C Fs = fma(ph.c9g[i], eu, -ph.w[WCLS(i)] * ug3[k]);
-      const C even = fma(ph.omega, sym, ph.fcoef * Fs);
+      const C sym = pp->w[WCLS(i)] * fma(pp->rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
+      const C Fs = fma(pp->c9g[i], eu, -pp->w[WCLS(i)] * ug3[k]);
+      const C even = fma(pp->omega, sym, pp->fcoef * Fs);
       if constexpr (HYB) {
-        const double odd = fma(ph.domega, ph.dc3w[WCLS(i)] * deu, ph.dcfa[i]);
+        const double odd = fma(pp->domega, pp->dc3w[WCLS(i)] * deu, pp->dcfa[i]);
         const double ev = (double)even;
-        o0[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i][k]), ev + odd));
-        o1[k] = from_c<PREC, double>(fma(ph.domc, (double)to_c<PREC, C>(W[i + 1][k]), ev - odd));
+        o0[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[i][k]), ev + odd));
+        o1[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[i + 1][k]), ev - odd));
       } else {
-        const C odd = fma(ph.omega, ph.c3w[WCLS(i)] * eu, ph.cfa[i]);
-        o0[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i][k]), even + odd));
-        o1[k] = from_c<PREC, C>(fma(ph.omc, to_c<PREC, C>(W[i + 1][k]), even - odd));
+        const C odd = fma(pp->omega, pp->c3w[WCLS(i)] * eu, pp->cfa[i]);
+        o0[k] = from_c<PREC, C>(fma(pp->omc, to_c<PREC, C>(W[i][k]), even + odd));
+        o1[k] = from_c<PREC, C>(fma(pp->omc, to_c<PREC, C>(W[i + 1][k]), even - odd));
       }
     }
     store_dir(i, o0);

@@ -1136,6 +1136,16 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     off = roundup(off + (long long)kQ * B.Sf, 4096 / c->sbytes);
     B.mask = -1;
   }
+  // The sweep addresses a Block's arrays through buffer resources that each
+  // cover up to five population arrays (plus 32-bit row and lane offsets):
+  // six arrays of a Block, ghost layers included, must stay below 4 GiB.
+  for (const auto& B : c->bh)
+    if (6LL * B.Sf * c->sbytes >= 0xFFFFFFF0LL) {
+      lbm_destroy(c);
+      return fail(LBM_EINVAL, "Block too large: six population arrays of a Block (ghost layers included) "
+                              "must stay below 4 GiB (at most about 89 M cells in FP64, 178 M in FP32, "
+                              "357 M in 16-bit storage)");
+    }
   c->grid_elems = (size_t)off;
   c->x_even = true;
   for (const auto& B : c->bh)
@@ -1248,7 +1258,6 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
       if ((c->geo.open[0] && solid[r * nx]) || (c->geo.open[1] && solid[r * nx + nx - 1]))
         return fail(LBM_EINVAL, "solid cell on an open face");
   }
-  drop_graphs(c);
   bool any = false;
   long long nsolid = 0;
   if (solid) {
@@ -1256,6 +1265,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
       if (solid[k]) ++nsolid;
     any = nsolid > 0;
   }
+  drop_graphs(c);
   if (any) {
     if (!c->d_mask) {
       long long moff = 0;
@@ -1666,7 +1676,10 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, c->device));
   key << prop.gcnArchName << "|p" << c->prec << "m" << c->f64math << "o" << c->has_mask << "|" << c->p.dims[0]
-      << "x" << c->p.dims[1] << "x" << c->p.dims[2] << "|nb" << c->bh.size();
+      << "x" << c->p.dims[1] << "x" << c->p.dims[2] << "|nb" << c->bh.size() << "|f";
+  // face kinds (open faces restrict the sweep variants) and row padding
+  for (int f = 0; f < 6; ++f) key << (int)c->p.face[f];
+  key << "|r" << c->p.row_pad;
   {
     unsigned long long h = 1469598103934665603ULL;
     for (const auto& b : c->aabb)
@@ -1687,10 +1700,15 @@ lbm_status lbm_autotune(lbm_ctx* c, const char* cache_path, int32_t trial_steps,
       if (ls >> kk >> s.fused_exchange >> s.item_cells >> s.wg_size >> s.persistent >> s.graph_steps >>
           s.nontemporal >> s.cells_per_lane) {
         std::string err;
-        if (kk == k && sched_valid(s, err)) {
+        // a cached schedule this context refuses (a hand-edited or foreign
+        // line) is skipped, and the search runs
+        if (kk == k && sched_valid(s, err) && (s.cells_per_lane != 2 || vec2_allowed(c))) {
+          s.graph_steps = c->sched.graph_steps;
           lbm_status st = lbm_set_schedule(c, &s);
-          if (st == LBM_OK && chosen) *chosen = s;
-          return st;
+          if (st == LBM_OK) {
+            if (chosen) *chosen = s;
+            return st;
+          }
         }
       }
     }

@@ -343,53 +343,3 @@ class UNet:
               self.e2b: 2, self.dn2: 3, self.e3a: 3, self.e3b: 3, self.up2: 2, self.d2a: 2, self.d2b: 2,
               self.up1: 1, self.d1a: 1, self.d1b: 1, self.up0: 0, self.d0a: 0, self.d0b: 0, self.head: 0}
         return sum(l.flops(v[lv[l]]) for l in self.layers)
-
-
-def bench_layers(n=8, D=128, H=64, W=64, reps=5, log=print):
-    """Per-layer times of the three convolution kernels at the given shape
-    (HIP events on the current stream); returns a list of dicts with
-    TFLOP/s (2 * voxels * taps * Cin * Cout per kernel)."""
-    import torch
-    net = UNet(n, D, H, W, seed=1)
-    net.forward()
-    torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    L = lib()
-    rows = []
-
-    def timed(fn):
-        fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            fn()
-        e1.record(st)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    for name, l, x, y in net.io():
-        dx = Act(x.n, x.d, x.h, x.w, x.c)
-        fl = l.flops(y.n * y.d * y.h * y.w)
-        t_f = timed(lambda: l.forward(x, y))
-        t_d = timed(lambda: _ck(L.lbm_conv3d_bwd_data(y.ref, l.wt.data_ptr(), dx.ref, None, l.k, l.stride, 0, None),
-                                "lbm_conv3d_bwd_data"))
-        t_w = timed(lambda: _ck(L.lbm_conv3d_bwd_weight(x.ref, y.ref, l.gw.data_ptr(), l.gb.data_ptr(), l.k, l.stride,
-                                                        None), "lbm_conv3d_bwd_weight"))
-        r = dict(layer=name, cin=l.cin, cout=l.cout, k=l.k, stride=l.stride, out=(y.d, y.h, y.w), gflop=fl / 1e9,
-                 fwd_ms=t_f, bwd_data_ms=t_d, bwd_weight_ms=t_w, fwd_tflops=fl / t_f / 1e9,
-                 bwd_data_tflops=fl / t_d / 1e9, bwd_weight_tflops=fl / t_w / 1e9)
-        rows.append(r)
-        log(r)
-        del dx
-    tot = sum(r["gflop"] for r in rows)
-    for kind in ("fwd", "bwd_data", "bwd_weight"):
-        t = sum(r[kind + "_ms"] for r in rows)
-        log(dict(total=kind, gflop=tot, ms=t, tflops=tot / t))
-    return rows
-
-
-if __name__ == "__main__":
-    import json
-    import torch
-    torch.cuda.init()
-    bench_layers(log=lambda r: print(json.dumps(r), flush=True))

@@ -208,6 +208,56 @@ def test_open_velocity_inlet_and_pressure_outlet_reach_uniform_flow():
     assert np.abs(rho - rout).max() < 1e-12
 
 
+@pytest.mark.parametrize("g", [(0.0, 0.0, 0.0), (3e-4, -2e-4, 1e-4)])
+def test_open_velocity_face_first_step_closed_form(g):
+    # A uniform state f~* = f~eq(drho0, u0) in a duct periodic in y and z,
+    # a velocity inlet u_b != u0 on -x, a pressure outlet on +x.  In the first
+    # step a -x face cell pulls, along the five directions with e_x = +1,
+    # f~eq(drho_f, u_b) + f~*(x_f) - f~eq(drho_f, u_f) from the boundary node,
+    # with drho_f = drho0 and u_f = u0 - g/2 rebuilt from the stored
+    # post-collision state; the other 14 directions bring f~eq(drho0, u0).
+    # The lattice sums over those five directions (weights 1/18 and 4 x 1/36),
+    #   sum w = 1/6, sum w e = (1/6, 0, 0),
+    #   sum w e_x e_x = 1/6, sum w e_y e_y = sum w e_z e_z = 1/18,
+    #   sum w e_y (e.u)^2 = u_x u_y / 9 (and likewise for z),
+    # give the face cell's moments by hand:
+    #   drho = drho0 + rho0 [h(u_b) - h(u_f)],     h(u) = u_x/2 + u_x^2/2,
+    #   rho0 u = rho0 (u0 + g/2) + rho0 [h, k_y, k_z](u_b) - rho0 [h, k_y, k_z](u_f),
+    #   k_a(u) = u_a/6 + u_x u_a/2.
+    # The +x pressure face cells gain w-sums of (drho_out - drho0): density
+    # +(drho_out - drho0)/6 and x momentum -(drho_out - drho0)/6; every other
+    # cell keeps drho0 and u0 + g/2.
+    rho0, drho0, drho_out = 1.0, 2.5e-3, -1.5e-3
+    u0 = np.array([0.03, -0.012, 0.008])
+    ub = np.array([0.05, 0.02, -0.015])
+    nx, ny, nz = 6, 3, 4
+    o = oracle.OracleLBM((nx, ny, nz), walls=(True, False, False), tau=0.7, force=g,
+                         open_x={"-x": ("velocity", tuple(ub)), "+x": ("pressure", rho0 + drho_out)})
+    shape = (nz, ny, nx)
+    o.set_equilibrium(np.full(shape, rho0 + drho0), np.broadcast_to(u0[:, None, None, None], (3,) + shape))
+    o.step(1)
+    rho, u = o.macroscopic()
+    g = np.asarray(g)
+    uf = u0 - g / 2
+
+    def h(v):
+        return v[0] / 2 + v[0] ** 2 / 2
+
+    def k(v, a):
+        return v[a] / 6 + v[0] * v[a] / 2
+
+    exp_rho = np.full(shape, rho0 + drho0)
+    exp_u = np.broadcast_to((u0 + g / 2)[:, None, None, None], (3,) + shape).copy()
+    exp_rho[:, :, 0] += rho0 * (h(ub) - h(uf))
+    exp_u[0][:, :, 0] += h(ub) - h(uf)
+    exp_u[1][:, :, 0] += k(ub, 1) - k(uf, 1)
+    exp_u[2][:, :, 0] += k(ub, 2) - k(uf, 2)
+    exp_rho[:, :, nx - 1] += (drho_out - drho0) / 6
+    exp_u[0][:, :, nx - 1] -= (drho_out - drho0) / (6 * rho0)
+    assert np.abs(rho - exp_rho).max() < 1e-15
+    assert np.abs(u - exp_u).max() < 1e-15
+
+
 def test_couette_exact_linear_profile():
     # Moving +z wall, resting -z wall: the steady profile is linear with the
     # no-slip points half a cell outside the fluid (half-way bounce-back,

@@ -201,6 +201,19 @@ lbm_status lbm_residual_since_mark(lbm_ctx* c, double* r, int64_t* nsteps);
 
 /* Global FP64 sums over fluid cells: mass = sum rho, mom = sum rho0 u. */
 lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]);
+/* lbm_sums for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and errors as lbm_sums, bit for bit, but the
+ * reduction's scratch (per-workgroup partials and the final sums, at most
+ * 6 x 1024 + 8 doubles; larger needs are refused with LBM_EINVAL) lives in
+ * one static device array per GPU that the library holds until the process
+ * ends, so the call allocates nothing (the context, made earlier, owns all
+ * other device memory).  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (nothing in it needs to start at zero):
+ * calls that overlap on one GPU, from several threads or contexts, race.
+ * Synchronises the context's stream.  LBM_EDEVICE if the array's address
+ * cannot be obtained. */
+lbm_status lbm_sums_noalloc(lbm_ctx* c, double* mass, double mom[3]);
 
 /* Checkpoint: the current post-collision populations, 19 x N in [i][z][y][x],
  * host buffer; as_fp64 = 1: FP64 values, 0: the storage type's raw values

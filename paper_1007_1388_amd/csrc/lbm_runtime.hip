@@ -15,6 +15,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -873,7 +874,11 @@ long long row_pad_lines(const lbm_params& p, long long row_bytes) {
   return 0;
 }
 
-lbm_status reduce(lbm_ctx* c, int want_prev, double out[6]) {
+// partials / red: the reduction's scratch (the context's own buffers, or
+// the allocation-free entry point's device array with room for nparts_max
+// workgroups)
+lbm_status reduce(lbm_ctx* c, int want_prev, double out[6], double* partials = nullptr, double* red = nullptr,
+                  int nparts_max = 0) {
   lbm_status hs = host_push(c);
   if (hs != LBM_OK) return hs;
   double hc[3], hp[3];
@@ -881,14 +886,43 @@ lbm_status reduce(lbm_ctx* c, int want_prev, double out[6]) {
   half_force(c, c->steps >= 2, hp);
   const CellArgs a = cell_args(c);
   const int nparts = std::max(1, std::min(c->nparts, a.nitems));
+  if (!partials) {
+    partials = c->d_partial;
+    red = c->d_red;
+  } else if (nparts > nparts_max) {
+    return fail(LBM_EINVAL, "reduction needs more workgroup partials than the scratch array holds");
+  }
   launch_reduce(c->prec, c->grid[c->cur], c->grid[1 - c->cur], a, c->p.rho0, hc, hp, want_prev,
-                want_prev == 2 ? c->d_umark + c->n_cells : nullptr, c->n_cells, c->d_partial, nparts, c->d_red,
-                c->stream);
+                want_prev == 2 ? c->d_umark + c->n_cells : nullptr, c->n_cells, partials, nparts, red, c->stream);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(out, c->d_red, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(out, red, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(out[k])) return fail(LBM_EUNSTABLE, "non-finite global sum");
+  return LBM_OK;
+}
+
+// Scratch of the allocation-free reductions (lbm_sums_noalloc): the
+// per-workgroup partials (6 doubles each, at most 1024 workgroups) and the
+// six final sums, in one file-scope device array per GPU.  Host code never
+// uses the array's name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchDoubles = 6 * 1024 + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+double* g_scratch_dev[64] = {};
+
+lbm_status scratch_ptr(int dev, double** out) {
+  if (dev < 0 || dev >= 64) return fail(LBM_EDEVICE, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
   return LBM_OK;
 }
 
@@ -1456,6 +1490,22 @@ lbm_status lbm_sums(lbm_ctx* c, double* mass, double mom[3]) {
   if (!c || !mass || !mom) return fail(LBM_EINVAL, "NULL argument");
   double s[6];
   lbm_status st = reduce(c, 0, s);
+  if (st != LBM_OK) return st;
+  *mass = (double)c->n_fluid * c->p.rho0 + s[0];
+  mom[0] = s[1];
+  mom[1] = s[2];
+  mom[2] = s[3];
+  return LBM_OK;
+}
+
+lbm_status lbm_sums_noalloc(lbm_ctx* c, double* mass, double mom[3]) {
+  if (!c || !mass || !mom) return fail(LBM_EINVAL, "NULL argument");
+  double* sp = nullptr;
+  lbm_status st = scratch_ptr(c->device, &sp);
+  if (st != LBM_OK) return st;
+  constexpr int kMaxParts = (int)((kScratchDoubles - 8) / 6);
+  double s[6];
+  st = reduce(c, 0, s, sp, sp + 6 * kMaxParts, kMaxParts);
   if (st != LBM_OK) return st;
   *mass = (double)c->n_fluid * c->p.rho0 + s[0];
   mom[0] = s[1];

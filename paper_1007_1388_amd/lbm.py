@@ -75,7 +75,7 @@ class lbm_info(ctypes.Structure):
 # The exported symbols of include/lbm.h, in declaration order.
 SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step",
            "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
-           "lbm_sums", "lbm_get_state", "lbm_set_state",
+           "lbm_sums", "lbm_sums_noalloc", "lbm_get_state", "lbm_set_state",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_set_host_blocks", "lbm_step_host_timed",
            "lbm_balance_host_blocks", "lbm_autotune", "lbm_info_get", "lbm_destroy",
            "lbm_strerror", "lbm_last_error", "lbm_bw_probe", "lbm_hbm_probe"]
@@ -110,6 +110,7 @@ def load(path=LIB_PATH):
         "lbm_residual_mark": [P],
         "lbm_residual_since_mark": [P, dp, ctypes.POINTER(ctypes.c_int64)],
         "lbm_sums": [P, dp, dp],
+        "lbm_sums_noalloc": [P, dp, dp],
         "lbm_get_state": [P, P, ctypes.c_int32],
         "lbm_set_state": [P, P, ctypes.c_int32],
         "lbm_get_schedule": [P, ctypes.POINTER(lbm_schedule)],
@@ -212,6 +213,14 @@ def lbm_sums(ctx):
     p = (ctypes.c_double * 3)()
     _check(load().lbm_sums(ctx, ctypes.byref(m), p), "lbm_sums")
     return m.value, np.array(list(p))
+
+
+def lbm_sums_noalloc(ctx):
+    """lbm_sums with the reduction scratch in the library's static device array."""
+    m = ctypes.c_double()
+    p = (ctypes.c_double * 3)()
+    _check(load().lbm_sums_noalloc(ctx, ctypes.byref(m), p), "lbm_sums_noalloc")
+    return m.value, np.array(p[:])
 
 
 def lbm_get_state(ctx, out, as_fp64):

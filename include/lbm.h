@@ -163,6 +163,17 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u);
  * the ghost exchange, and with open faces the fill of their boundary nodes)
  * on the context stream.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* c, int64_t n);
+/* Advance n steps as persistent launches of steps_per_launch steps each (the
+ * last one shorter): one workgroup per resident slot walks the Blocks' work
+ * items (the block list) step after step, with the ghost exchange fused into
+ * the sweep and a grid-wide barrier between steps (a cooperative launch:
+ * every workgroup is resident).  Same results as lbm_step, bit for bit;
+ * stream-ordered and asynchronous like lbm_step (Sec. 4: a Sweep is exchange
+ * plus kernel; here one launch holds many of them).  LBM_EINVAL: n < 0,
+ * steps_per_launch outside [1, 2^20], Blocks on the host CPU, open faces, or
+ * a schedule with two cells per lane; LBM_EDEVICE if the cooperative launch
+ * fails. */
+lbm_status lbm_step_persistent(lbm_ctx* c, int64_t n, int32_t steps_per_launch);
 
 /* Advances n steps (1 <= n <= 100000) exactly as lbm_step does, launched one
  * by one (no graphs), with a HIP event pair around every sweep launch and

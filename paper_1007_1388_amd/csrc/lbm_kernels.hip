@@ -10,8 +10,10 @@
 // Precision variants (template PREC): 0 FP64, 1 FP32, 2 shifted FP16,
 // 3 shifted BF16 (storage), arithmetic type C = double or float.
 #include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
 #include <climits>
+#include <algorithm>
 
 #include "lbm_internal.h"
 
@@ -338,8 +340,9 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
-__device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& ph_in, const BlockDev& B_in, int bid,
-                                          int z, int y0w, int seg, int yend, int xw, const GhostTgt* gts) {
+__device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& ph_in, const void* src_grid, void* dst_grid,
+                                          const BlockDev& B_in, int bid, int z, int y0w, int seg, int yend, int xw,
+                                          const GhostTgt* gts) {
   // The kernel's arguments (this sweep's pointers, the geometry and the
   // physical constants) are read through the kernel-argument segment at the
   // point of use, here and again after the pull phase, instead of being
@@ -370,8 +373,8 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
     B.Ry = sgpr_launder(B.Ry);
   }
   using T = typename Stor<PREC>::T;
-  const T* __restrict__ src = (const T*)pa->src;
-  T* __restrict__ dst = (T*)pa->dst;
+  const T* __restrict__ src = (const T*)src_grid;
+  T* __restrict__ dst = (T*)dst_grid;
   const int lane = threadIdx.x & 63;
   const int a = B.dim[0], b = B.dim[1], c = B.dim[2];
   const int r = lane / xw;
@@ -387,7 +390,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   // (laundered here so that the compiler does not keep ten resources and
   // some forty offsets of an item live across its rows, which spills scalar
   // registers into vector lanes).
-  long long gsrc = (long long)(uintptr_t)pa->src, gdst = (long long)(uintptr_t)pa->dst, gbase = B.base;
+  long long gsrc = (long long)(uintptr_t)src_grid, gdst = (long long)(uintptr_t)dst_grid, gbase = B.base;
   if constexpr (VEC == 1 && BLAUNDER) {
     asm volatile("" : "+s"(gsrc), "+s"(gdst), "+s"(gbase));
   }
@@ -847,15 +850,14 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   }
 }
 
-// At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
-// OPEN: contexts with open x faces (one cell per lane).
+// The work items of one sweep from src to dst, workgroup by workgroup
+// (item w, w + grid, ...); the waves of a workgroup take an item's
+// (row group, 64-lane segment) tasks in turn.
 template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
-k_sweep(const SweepArgs A, const Phys<C> ph) {
+__device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& ph, const void* src, void* dst,
+                                            GhostTgt* gts) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
-  // ghost targets of the current item's Block (fused exchange)
-  __shared__ GhostTgt gts[FX == 1 ? 27 : 1];
   for (int it = blockIdx.x; it < A.nitems; it += gridDim.x) {
     const ItemDev item = A.items[it];
     if constexpr (FX == 1) {
@@ -875,9 +877,41 @@ k_sweep(const SweepArgs A, const Phys<C> ph) {
     const int yend = item.y0 + item.nrows;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, B, item.block, item.z, item.y0 + grp * rpw, seg, yend, xw,
-                                                  gts);
+      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + grp * rpw, seg,
+                                                  yend, xw, gts);
     }
+  }
+}
+
+// At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
+// OPEN: contexts with open x faces (one cell per lane).
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
+k_sweep(const SweepArgs A, const Phys<C> ph) {
+  // ghost targets of the current item's Block (fused exchange)
+  __shared__ GhostTgt gts[FX == 1 ? 27 : 1];
+  sweep_items<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, A.src, A.dst, gts);
+}
+
+// Several steps in one launch: a persistent block-list kernel.  Every
+// workgroup walks the item list once per step, the ghost exchange is fused
+// into the sweep (every boundary value goes straight into the neighbours'
+// ghost layers), the two grids swap roles from step to step, and a
+// grid-wide barrier (agent-scope release and acquire, so the ghost values
+// written on one XCD are seen on the others) separates the steps.  The
+// launch is cooperative: every workgroup is resident, so the barrier never
+// waits on one that has not started, and every workgroup passes every
+// barrier (its item loop may be empty).
+template <int PREC, typename C, bool MASK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_sweep_steps(const SweepArgs A, const Phys<C> ph, int nsteps) {
+  __shared__ GhostTgt gts[27];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int s = 0; s < nsteps; ++s) {
+    const void* src = (s & 1) ? (const void*)A.dst : A.src;
+    void* dst = (s & 1) ? const_cast<void*>(A.src) : A.dst;
+    sweep_items<PREC, C, MASK, 1, true, 1, false>(A, ph, src, dst, gts);
+    grid.sync();
   }
 }
 
@@ -1365,6 +1399,38 @@ void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, c
     default: fn = v ? pick3<3, float, 2>(mask, fx, nt) : pick3<3, float, 1>(mask, fx, nt); break;
   }
   fn(a, pd, pf, grid, block, s);
+}
+
+// The persistent multi-step sweep: grid = the largest number of its
+// workgroups the GPU holds at once (at most one per item), launched
+// cooperatively.  Returns the HIP error of the launch.
+template <int PREC, typename C, bool MASK>
+static hipError_t launch_steps_t(const SweepArgs& a, const Phys<C>& ph, int nsteps, int cus, hipStream_t s) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep_steps<PREC, C, MASK>, 256, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int grid = std::max(1, std::min(a.nitems, per_cu * cus));
+  SweepArgs aa = a;
+  Phys<C> pp = ph;
+  int n = nsteps;
+  void* args[] = {&aa, &pp, &n};
+  return hipLaunchCooperativeKernel((const void*)k_sweep_steps<PREC, C, MASK>, dim3(grid), dim3(256), args, 0, s);
+}
+
+hipError_t launch_sweep_steps(int prec, bool f64math, bool mask, const SweepArgs& a, const Phys<double>& pd,
+                              const Phys<float>& pf, int nsteps, int cus, hipStream_t s) {
+#define LBM_STEPS(P, CT, PH)                                                               \
+  return mask ? launch_steps_t<P, CT, true>(a, PH, nsteps, cus, s) : launch_steps_t<P, CT, false>(a, PH, nsteps, cus, s)
+  switch (prec) {
+    case 0: LBM_STEPS(0, double, pd);
+    case 1:
+      if (f64math) LBM_STEPS(1, double, pd);
+      LBM_STEPS(1, float, pf);
+    case 2: LBM_STEPS(2, float, pf);
+    default: LBM_STEPS(3, float, pf);
+  }
+#undef LBM_STEPS
 }
 
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,

@@ -28,6 +28,8 @@ namespace lbm {
 void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
 bool sweep_vec2_ok(int prec, bool f64math);
+hipError_t launch_sweep_steps(int prec, bool f64math, bool mask, const SweepArgs& a, const Phys<double>& pd,
+                              const Phys<float>& pf, int nsteps, int cus, hipStream_t s);
 void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev* nbr, const XchgTask* tasks,
                      int ntasks, hipStream_t s);
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
@@ -1369,6 +1371,30 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   return run_steps(c, n);
+}
+
+lbm_status lbm_step_persistent(lbm_ctx* c, int64_t n, int32_t steps_per_launch) {
+  if (!c || n < 0) return fail(LBM_EINVAL, "NULL context or negative step count");
+  if (hetero(c)) return fail(LBM_EINVAL, "the persistent sweep runs every Block on the GPU");
+  if (has_open(c)) return fail(LBM_EINVAL, "the persistent sweep has no pass for the boundary nodes of open faces");
+  if (cells_per_lane(c, c->sched) != 1) return fail(LBM_EINVAL, "the persistent sweep takes one cell per lane");
+  if (steps_per_launch < 1 || steps_per_launch > (1 << 20))
+    return fail(LBM_EINVAL, "steps_per_launch must be in [1, 2^20]");
+  while (n > 0) {
+    const int k = (int)std::min<int64_t>(n, steps_per_launch);
+    const SweepArgs a = sweep_args(c, c->cur);
+    if (a.nitems > 0) {
+      hipError_t e = launch_sweep_steps(c->prec, c->f64math, c->has_mask, a, c->phd, c->phf, k, c->cu_count,
+                                        c->stream);
+      if (e != hipSuccess)
+        return fail(LBM_EDEVICE, std::string("cooperative launch of the persistent sweep: ") + hipGetErrorString(e));
+    }
+    if (k & 1) c->cur = 1 - c->cur;
+    c->steps += k;
+    n -= k;
+  }
+  HIPCHK(hipGetLastError());
+  return LBM_OK;
 }
 
 lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* sweep_ms, double* exchange_ms) {

@@ -73,7 +73,7 @@ class lbm_info(ctypes.Structure):
 
 
 # The exported symbols of include/lbm.h, in declaration order.
-SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step",
+SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step", "lbm_step_persistent",
            "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
            "lbm_sums", "lbm_sums_noalloc", "lbm_get_state", "lbm_set_state",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_set_host_blocks", "lbm_step_host_timed",
@@ -104,6 +104,7 @@ def load(path=LIB_PATH):
         "lbm_set_geometry": [P, P],
         "lbm_set_equilibrium": [P, dp, dp],
         "lbm_step": [P, ctypes.c_int64],
+        "lbm_step_persistent": [P, ctypes.c_int64, ctypes.c_int32],
         "lbm_step_timed": [P, ctypes.c_int64, dp, dp],
         "lbm_macroscopic": [P, P, P, ctypes.c_int32],
         "lbm_residual": [P, dp],
@@ -177,6 +178,10 @@ def lbm_set_equilibrium(ctx, rho, u):
 
 def lbm_step(ctx, n):
     _check(load().lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_step_persistent(ctx, n, steps_per_launch):
+    _check(load().lbm_step_persistent(ctx, int(n), int(steps_per_launch)), "lbm_step_persistent")
 
 
 def lbm_step_timed(ctx, n):
@@ -424,6 +429,10 @@ class Lattice:
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
+
+    def step_persistent(self, n, steps_per_launch=100):
+        """n steps as persistent launches (grid barrier per step, fused exchange)."""
+        lbm_step_persistent(self.ctx, n, steps_per_launch)
 
     def step_timed(self, n):
         """Advance n steps launch by launch; returns (sweep ms, exchange ms)

@@ -71,8 +71,10 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_preci
  * prescribes u_b = wall_u[face] and takes drho_b = drho_f; PRESSURE
  * prescribes rho_b = face_rho[face] and takes u_b = u_f.  A link whose
  * source lies beyond a WALL face as well bounces back (walls take
- * precedence).  Open faces need nx >= 2, one Block across y and across z,
- * and no solid cell on the face; their contexts run one cell per lane. */
+ * precedence).  Open faces need nx >= 2 and no solid cell on the face; the
+ * Blocks may be cut across y and z (a boundary node feeds the face cells of
+ * the Blocks next to it through their ghost rows); their contexts run one
+ * cell per lane. */
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_VELOCITY = 2, LBM_PRESSURE = 3 } lbm_face;
 
 /* Half-open global cell box [lo, hi) of one Block (the Block AABB, Sec. 4.2). */

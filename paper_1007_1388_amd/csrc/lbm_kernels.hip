@@ -1042,45 +1042,6 @@ __global__ void __launch_bounds__(256) k_linkmask(const uint8_t* __restrict__ so
   }
 }
 
-// Boundary nodes of open x faces next to cell (x, y, z) of B (global x gx):
-// from its stored post-collision populations (drho = sum f~,
-// u = sum e f~ / rho0 - g/2, the collision invariants), each population that
-// enters the domain through the face, f~_q + open_corr, into the x-ghost slot
-// of the cell's own row (an interior row: no wall bounce-back slot lies
-// there).  FP64 arithmetic.
-template <int PREC>
-__device__ __forceinline__ void open_fill(typename Stor<PREC>::T* grid, const GridGeom& geo, const BlockDev& B, int x,
-                                          int y, int z, int gx) {
-  using T = typename Stor<PREC>::T;
-  const bool lo = geo.open[0] && gx == 0, hi = geo.open[1] && gx == geo.n[0] - 1;
-  if (!(lo || hi)) return;
-  double f[kQ], d = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-  for (int i = 0; i < kQ; ++i) {
-    f[i] = (double)to_c<PREC, double>(grid[main_off(B, i, x, y, z)]);
-    d += f[i];
-    jx += EXd(i) * f[i];
-    jy += EYd(i) * f[i];
-    jz += EZd(i) * f[i];
-  }
-  const double r0 = geo.rho0;
-  const double ux = jx / r0 - geo.hg[0], uy = jy / r0 - geo.hg[1], uz = jz / r0 - geo.hg[2];
-  // On a periodic y or z axis the node is also the periodic image of the
-  // ghost row beyond the opposite face (cell (0, 0, z) pulls e = (1, 1, 0)
-  // from (-1, -1, z) = (-1, ny - 1, z)); the Block spans the whole axis, so
-  // no exchange fills those rows, and no wall slot lies in them.
-  const int ny = B.dim[1], nz = B.dim[2];
-  const int y2 = !geo.wall[1] && y == ny - 1 ? -1 : (!geo.wall[1] && y == 0 ? ny : INT_MIN);
-  const int z2 = !geo.wall[2] && z == nz - 1 ? -1 : (!geo.wall[2] && z == 0 ? nz : INT_MIN);
-  for (int i = 1; i < kQ; ++i) {
-    if ((EXd(i) > 0 && lo) || (EXd(i) < 0 && hi)) {
-      const T v = from_c<PREC, double>(f[i] + open_corr(geo, EXd(i) > 0 ? 0 : 1, i, r0, d, ux, uy, uz));
-      grid[xg_off(B, i, y, z)] = v;
-      if (y2 != INT_MIN) grid[xg_off(B, i, y2, z)] = v;
-      if (z2 != INT_MIN) grid[xg_off(B, i, y, z2)] = v;
-    }
-  }
-}
-
 // Bounce-back slots of a state loaded from outside the sweep (rest state,
 // warm start, checkpoint): for every wall link of a fluid cell x, slot
 // (x - e_i, i) = f_ibar(x) + 6 w_i rho0 e_i.u_w, rounded as the sweep rounds
@@ -1118,42 +1079,99 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
       if (moving && bw) v = from_c<PREC, C>(to_c<PREC, C>(v) + wall_corr<C, 1>(sa, ph, wf, i, 0));
       grid[o] = v;
     }
-    open_fill<PREC>(grid, A.geo, B, x, y, z, gx);
   });
 }
 
-// Open x faces, once per step after the sweep: the boundary nodes beyond the
-// open faces from the face cells' moments and entering populations that the
-// sweep left in `side` (the moments of their collision, as the boundary rule
-// asks).  One thread per face cell, consecutive threads consecutive y.
+// Open x faces, once per step after the sweep (and after a state is loaded,
+// from k_openside): the boundary nodes beyond the open faces from the face
+// cells' moments and entering populations in `side` (the moments of their
+// collision, as the boundary rule asks).  A boundary node at (-1 or nx, y, z)
+// feeds the face cells around (y, z), so its value goes into the x-ghost
+// plane of every face Block whose plane, ghost rows included, covers (y, z):
+// the Block that owns the face cell and the face Blocks next to it across y
+// or z (and, on a periodic axis, the Blocks holding its periodic image in
+// their ghost rows).  One thread per node position (y, z) in [-1, ny] x
+// [-1, nz] of each face; nodes beyond a wall are left to the sweep's
+// bounce-back.  faceblk: per face the count of Blocks touching it, then
+// their ids (stride 1 + nblocks).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_openfill(void* grid_, const BlockDev* __restrict__ blocks, int nblocks,
-                                                  GridGeom geo, const double* __restrict__ side) {
+                                                  const int* __restrict__ faceblk, GridGeom geo,
+                                                  const double* __restrict__ side) {
   using T = typename Stor<PREC>::T;
   T* grid = (T*)grid_;
+  const int ny = geo.n[1], nz = geo.n[2];
+  const int per_face = (ny + 2) * (nz + 2);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * per_face) return;
+  const int f = t / per_face, yz = t % per_face;
+  if (!geo.open[f]) return;
+  const int gy = yz % (ny + 2) - 1, gz = yz / (ny + 2) - 1;
+  if ((gy < 0 || gy >= ny) && geo.wall[1]) return;
+  if ((gz < 0 || gz >= nz) && geo.wall[2]) return;
+  const int sy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+  const int sz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);
+  const double* cs = side + 16 * ((long long)f * ny * nz + (long long)sz * ny + sy);
+  const double d = cs[5], ux = cs[6], uy = cs[7], uz = cs[8];
+  T v[5];
+  for (int slot = 0; slot < 5; ++slot) {
+    const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
+    v[slot] = from_c<PREC, double>(cs[slot] + open_corr(geo, f, q, geo.rho0, d, ux, uy, uz));
+  }
+  const int* list = faceblk + f * (1 + nblocks);
+  for (int k = 0; k < list[0]; ++k) {
+    const BlockDev& M = blocks[list[1 + k]];
+    const int ly = gy - M.org[1], lz = gz - M.org[2];
+    if (ly < -1 || ly > M.dim[1] || lz < -1 || lz > M.dim[2]) continue;
+    for (int slot = 0; slot < 5; ++slot) {
+      const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
+      grid[xg_off(M, q, ly, lz)] = v[slot];
+    }
+  }
+}
+
+// After a state is loaded (rest state, warm start, checkpoint): the face
+// cells' entries of `side` rebuilt from their stored post-collision
+// populations (drho = sum f~, u = sum e f~ / rho0 - g/2: the collision
+// invariants, so the moments of their last collision up to rounding), in the
+// layout the sweep writes, for k_openfill.  One thread per face cell (FP64).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_openside(const void* grid_, const BlockDev* __restrict__ blocks,
+                                                  int nblocks, const int* __restrict__ faceblk, GridGeom geo,
+                                                  double* __restrict__ side) {
+  using T = typename Stor<PREC>::T;
+  const T* grid = (const T*)grid_;
   const int ny = geo.n[1], nz = geo.n[2];
   const int per_face = ny * nz;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * per_face) return;
   const int f = t / per_face, yz = t % per_face;
   if (!geo.open[f]) return;
-  const int y = yz % ny, z = yz / ny;
-  const int gx = f == 0 ? 0 : geo.n[0] - 1;
-  int j = 0;
-  while (j < nblocks && !(gx >= blocks[j].org[0] && gx < blocks[j].org[0] + blocks[j].dim[0])) ++j;
-  if (j == nblocks) return;
-  const BlockDev& B = blocks[j];
-  const double* cs = side + 16 * ((long long)f * per_face + yz);
-  auto at = [&](int slot) { return cs[slot]; };
-  const double d = at(5), ux = at(6), uy = at(7), uz = at(8);
-  const int y2 = !geo.wall[1] && y == ny - 1 ? -1 : (!geo.wall[1] && y == 0 ? ny : INT_MIN);
-  const int z2 = !geo.wall[2] && z == nz - 1 ? -1 : (!geo.wall[2] && z == 0 ? nz : INT_MIN);
-  for (int slot = 0; slot < 5; ++slot) {
-    const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
-    const T v = from_c<PREC, double>(at(slot) + open_corr(geo, f, q, geo.rho0, d, ux, uy, uz));
-    grid[xg_off(B, q, y, z)] = v;
-    if (y2 != INT_MIN) grid[xg_off(B, q, y2, z)] = v;
-    if (z2 != INT_MIN) grid[xg_off(B, q, y, z2)] = v;
+  const int gy = yz % ny, gz = yz / ny;
+  const int* list = faceblk + f * (1 + nblocks);
+  for (int k = 0; k < list[0]; ++k) {
+    const BlockDev& B = blocks[list[1 + k]];
+    const int y = gy - B.org[1], z = gz - B.org[2];
+    if (y < 0 || y >= B.dim[1] || z < 0 || z >= B.dim[2]) continue;
+    const int x = f == 0 ? 0 : B.dim[0] - 1;
+    double fi[kQ], dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int i = 0; i < kQ; ++i) {
+      fi[i] = (double)to_c<PREC, double>(grid[main_off(B, i, x, y, z)]);
+      dr += fi[i];
+      jx += EXd(i) * fi[i];
+      jy += EYd(i) * fi[i];
+      jz += EZd(i) * fi[i];
+    }
+    double* cs = side + 16 * ((long long)f * per_face + yz);
+    for (int slot = 0; slot < 5; ++slot) {
+      const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
+      cs[slot] = fi[q];
+    }
+    cs[5] = dr;
+    cs[6] = jx / geo.rho0 - geo.hg[0];
+    cs[7] = jy / geo.rho0 - geo.hg[1];
+    cs[8] = jz / geo.rho0 - geo.hg[2];
+    for (int j = 9; j < 16; ++j) cs[j] = 0.0;
   }
 }
 
@@ -1479,15 +1497,27 @@ void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const 
   }
 }
 
-void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo,
-                     const double* side, hipStream_t s) {
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
+                     const GridGeom& geo, const double* side, hipStream_t s) {
+  const int n = 2 * (geo.n[1] + 2) * (geo.n[2] + 2);
+  const dim3 g((n + 255) / 256), b(256);
+  switch (prec) {
+    case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    case 1: hipLaunchKernelGGL(k_openfill<1>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    case 2: hipLaunchKernelGGL(k_openfill<2>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    default: hipLaunchKernelGGL(k_openfill<3>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+  }
+}
+
+void launch_openside(int prec, const void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
+                     const GridGeom& geo, double* side, hipStream_t s) {
   const int n = 2 * geo.n[1] * geo.n[2];
   const dim3 g((n + 255) / 256), b(256);
   switch (prec) {
-    case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
-    case 1: hipLaunchKernelGGL(k_openfill<1>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
-    case 2: hipLaunchKernelGGL(k_openfill<2>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
-    default: hipLaunchKernelGGL(k_openfill<3>, g, b, 0, s, grid, blocks, nblocks, geo, side); break;
+    case 0: hipLaunchKernelGGL(k_openside<0>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    case 1: hipLaunchKernelGGL(k_openside<1>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    case 2: hipLaunchKernelGGL(k_openside<2>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
+    default: hipLaunchKernelGGL(k_openside<3>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
   }
 }
 

@@ -35,8 +35,10 @@ void launch_exchange(int prec, void* grid, const BlockDev* blocks, const NbrDev*
 void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const Phys<double>& pd,
                    const Phys<float>& pf, hipStream_t s);
 void launch_linkmask(const uint8_t* solid, const CellArgs& a, uint32_t* mask, hipStream_t s);
-void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const GridGeom& geo,
-                     const double* side, hipStream_t s);
+void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
+                     const GridGeom& geo, const double* side, hipStream_t s);
+void launch_openside(int prec, const void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
+                     const GridGeom& geo, double* side, hipStream_t s);
 void launch_init_eq(int prec, void* grid, const CellArgs& a, double rho0, const double* rho, const double* u,
                     long long N, hipStream_t s);
 void launch_macro(int prec, const void* grid, const CellArgs& a, double rho0, const double hg[3], double* rho,
@@ -125,6 +127,7 @@ struct lbm_ctx {
   int nparts = 1024;
   double* d_red = nullptr;
   double* d_side = nullptr;  // open x faces: [face][nz][ny][16] (see SweepArgs::side)
+  int* d_faceblk = nullptr;  // open x faces: per face the count of Blocks touching it, then their ids
   void* d_stage = nullptr;
   double* d_umark = nullptr;   // [rho | u_x | u_y | u_z] snapshot, FP64, 4 N
   long long mark_steps = -1;   // step count of the snapshot, -1 = none
@@ -492,10 +495,23 @@ void enqueue_exchange(lbm_ctx* c, int g, hipStream_t s, bool rim = false) {
     launch_exchange(c->prec, c->grid[g], c->d_blocks, c->d_nbr, c->d_tasks, (int)c->tasks_h.size(), s);
 }
 
+bool has_open(const lbm_ctx* c);
+
+// Bounce-back slots and the open faces' boundary nodes of a state written
+// from outside the sweep (the nodes from the face cells' stored populations).
+void enqueue_slots(lbm_ctx* c, int g, hipStream_t s) {
+  launch_bbfill(c->prec, c->f64math, c->grid[g], cell_args(c), c->phd, c->phf, s);
+  if (has_open(c)) {
+    const int nb = (int)c->bh.size();
+    launch_openside(c->prec, c->grid[g], c->d_blocks, nb, c->d_faceblk, c->geo, c->d_side, s);
+    launch_openfill(c->prec, c->grid[g], c->d_blocks, nb, c->d_faceblk, c->geo, c->d_side, s);
+  }
+}
+
 // Ghost layers and bounce-back slots of a state written from outside the sweep.
 void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
   enqueue_exchange(c, g, s);
-  launch_bbfill(c->prec, c->f64math, c->grid[g], cell_args(c), c->phd, c->phf, s);
+  enqueue_slots(c, g, s);
 }
 
 // Cells per lane the sweep of schedule s runs with (0 = automatic = one: with
@@ -526,7 +542,8 @@ bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
 // and the boundary nodes of open faces.
 void enqueue_post(lbm_ctx* c, int g, hipStream_t s) {
   if (c->sched.fused_exchange != 1) enqueue_exchange(c, g, s, c->sched.fused_exchange == 2);
-  if (has_open(c)) launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->geo, c->d_side, s);
+  if (has_open(c))
+    launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->d_faceblk, c->geo, c->d_side, s);
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
@@ -1032,8 +1049,6 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   std::vector<int> cuts[3], owner;
   std::string err;
   if (!build_tiling(p->dims, blocks, nblocks, cuts, owner, err)) return fail(LBM_EINVAL, err);
-  if (any_open && (cuts[1].size() != 2 || cuts[2].size() != 2))
-    return fail(LBM_EINVAL, "open x faces need one Block across y and across z");
   if (any_open && p->dims[0] < 2) return fail(LBM_EINVAL, "open x faces need nx >= 2");
 
   lbm_ctx* c = new lbm_ctx();
@@ -1263,8 +1278,9 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->d_red = (double*)dalloc(c, sizeof(double) * 8);
   if (c->geo.open[0] || c->geo.open[1])
     c->d_side = (double*)dalloc(c, sizeof(double) * 32 * (size_t)p->dims[1] * p->dims[2]);
+    c->d_faceblk = (int*)dalloc(c, sizeof(int) * 2 * (1 + (size_t)nblocks));
   if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_rim ||
-      !c->d_partial || !c->d_red || ((c->geo.open[0] || c->geo.open[1]) && !c->d_side))
+      !c->d_partial || !c->d_red || ((c->geo.open[0] || c->geo.open[1]) && (!c->d_side || !c->d_faceblk)))
     return bail(LBM_ENOMEM, "device allocation failed");
   if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1275,10 +1291,25 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       (!c->rim_h.empty() && hipMemcpy(c->d_rim, c->rim_h.data(), sizeof(XchgTask) * c->rim_h.size(),
                                       hipMemcpyHostToDevice) != hipSuccess))
     return bail(LBM_EDEVICE, "upload of block tables failed");
+  if (c->d_faceblk) {
+    // the Blocks touching each open x face
+    std::vector<int> fl((size_t)2 * (1 + nblocks), 0);
+    for (int f = 0; f < 2; ++f)
+      for (int j = 0; j < nblocks; ++j) {
+        const BlockDev& B = c->bh[j];
+        if (f == 0 ? B.org[0] == 0 : B.org[0] + B.dim[0] == p->dims[0]) {
+          int* list = fl.data() + (size_t)f * (1 + nblocks);
+          list[1 + list[0]] = j;
+          ++list[0];
+        }
+      }
+    if (hipMemcpy(c->d_faceblk, fl.data(), sizeof(int) * fl.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(LBM_EDEVICE, "upload of block tables failed");
+  }
   if (upload_items(c) != LBM_OK) return bail(LBM_ENOMEM, "item list upload failed");
   if (zero_grids(c) != LBM_OK) return bail(LBM_EDEVICE, "grid initialisation failed");
   // rest state: bounce-back slots of moving walls carry the wall term
-  launch_bbfill(c->prec, c->f64math, c->grid[0], cell_args(c), c->phd, c->phf, c->stream);
+  enqueue_slots(c, 0, c->stream);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(LBM_EDEVICE, "grid initialisation failed");
   *out = c;
@@ -1330,7 +1361,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   c->n_fluid = c->n_cells - nsolid;
   lbm_status s = zero_grids(c);
   if (s != LBM_OK) return s;
-  launch_bbfill(c->prec, c->f64math, c->grid[0], cell_args(c), c->phd, c->phf, c->stream);
+  enqueue_slots(c, 0, c->stream);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->cur = 0;

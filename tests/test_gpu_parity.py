@@ -265,6 +265,54 @@ def test_open_faces_tilings_and_schedules_bitwise(variant):
         check_vs_oracle(f64, o, TOL["f64"])
 
 
+@pytest.mark.parametrize("variant", range(6))
+def test_open_faces_on_blocks_cut_across_y_and_z(variant):
+    """Open x faces on tilings cut across y and z: a boundary node feeds the
+    face cells of the Blocks next to it through their x-ghost planes' ghost
+    rows.  Bit for bit against the one-Block run (every exchange mode, graph
+    capture, uneven cuts, a periodic z axis), and FP64 against the oracle."""
+    dims = (29, 10, 9)
+    case = duct(dims=dims)
+    if variant == 5:
+        # periodic z and y: the boundary nodes' periodic images sit in ghost
+        # rows of the Blocks at the far side
+        case = duct(dims=dims)
+        case["walls"] = (True, False, False)
+        case.pop("wall_u")
+    blocks = [inputs.uniform_blocks(dims, (1, 2, 1)), inputs.uniform_blocks(dims, (1, 1, 3)),
+              inputs.uniform_blocks(dims, (3, 2, 3)),
+              [((x0, y0, z0), (x1, y1, z1)) for (x0, x1) in ((0, 11), (11, 29)) for (y0, y1) in ((0, 3), (3, 10))
+               for (z0, z1) in ((0, 4), (4, 9))],
+              inputs.uniform_blocks(dims, (2, 2, 2)), inputs.uniform_blocks(dims, (1, 2, 3))][variant]
+    sched = [dict(fused_exchange=0), dict(fused_exchange=1), dict(fused_exchange=2),
+             dict(fused_exchange=2, graph_steps=4), dict(fused_exchange=1, graph_steps=5), dict()][variant]
+    ref = run_gpu(case, 41, precision="f32")
+    lat = run_gpu(case, 41, blocks=blocks, precision="f32", schedule=sched)
+    assert np.array_equal(lat.get_state(as_fp64=False), ref.get_state(as_fp64=False))
+    f64 = run_gpu(case, 41, blocks=blocks, schedule=sched)
+    o = run_oracle(case, 41)
+    check_vs_oracle(f64, o, TOL["f64"])
+
+
+def test_open_faces_cut_tiling_checkpoint_restart():
+    """A state loaded into a cut tiling with open faces (set_state fills the
+    boundary nodes from the face cells' stored populations, whose moments
+    equal those of their last collision up to rounding) continues as the
+    uninterrupted run, to FP64 rounding."""
+    dims = (29, 10, 9)
+    case = duct(dims=dims)
+    blocks = inputs.uniform_blocks(dims, (2, 2, 3))
+    a = run_gpu(case, 30, blocks=blocks)
+    f = a.get_state(as_fp64=True)
+    b = gpu_lattice(case, blocks=inputs.uniform_blocks(dims, (1, 3, 1)))
+    prepare(b, case)
+    b.set_state(f, as_fp64=True)
+    a.step(20)
+    b.step(20)
+    fa, fb = a.get_state(as_fp64=True), b.get_state(as_fp64=True)
+    assert np.abs(fa - fb).max() <= 1e-12 * np.abs(fa).max()
+
+
 def test_open_faces_reject_solid_on_the_face():
     case = duct(obstacles=False)
     lat = gpu_lattice(case)

@@ -98,10 +98,12 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* user);  /* optional device allocator */
   void (*dev_free)(void* ptr, void* user);
   void* alloc_user;
-  int32_t row_pad;        /* x-row padding: every row of a Block array is rounded up to
-                             128 bytes and then row_pad more 128-byte lines are added;
-                             0 = automatic, -1 = none (layout only; results do not depend
-                             on it) */
+  int32_t row_pad;        /* x-row layout: 0 = automatic (rows rounded up to 128 bytes,
+                             except FP32/FP64 rows of an odd number of 64-byte halves on
+                             Blocks with an even y extent, packed two rows to three
+                             128-byte lines); -1 = every row rounded up to 128 bytes;
+                             n > 0 = rounded up, then n more 128-byte lines (layout only;
+                             results do not depend on it) */
   double face_rho[6];     /* PRESSURE faces: the prescribed density (> 0); ignored
                              on other faces */
 } lbm_params;
@@ -120,7 +122,9 @@ typedef struct {
   int32_t persistent;      /* 0: one workgroup per item; k > 0: k workgroups per
                               compute unit loop over the item list */
   int32_t graph_steps;     /* time steps per captured HIP graph; 0: plain launches */
-  int32_t nontemporal;     /* 1: streaming (non-temporal) loads and stores */
+  int32_t nontemporal;     /* 1: the sweep streams (non-temporal) its row stores; 0: ordinary
+                              stores.  Loads and values written one per row (walls, x-ghost
+                              planes) are ordinary either way.  Results do not depend on it. */
   int32_t cells_per_lane;  /* cells per lane along x: 0 = automatic (1); 1; or 2 (only for
                               F16S/BF16S and for F32 storage with FP64 arithmetic, with
                               every Block's x extent even and no open face, else

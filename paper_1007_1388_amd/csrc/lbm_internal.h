@@ -4,7 +4,8 @@
 // scheme, Sec. 2.1) the populations are stored Structure-of-Arrays
 // (Sec. 3.2): 19 arrays f_i[z][y][x] that include a one-cell ghost layer in y
 // and z (rows y = -1, b and planes z = -1, c), with x-rows padded to a
-// multiple of 128 bytes so every row starts on a cache line.  The ghost layer
+// multiple of 128 bytes so every row starts on a cache line, or, for rows of
+// an odd number of half lines, packed two rows to three lines (pack).  The ghost layer
 // in x lives in one extra plane per array, placed right after it: for the five
 // directions with e_x = +1 it holds x = -1, for the five with e_x = -1 it holds
 // x = a (Sec. 4.4 counts 5 PDFs per face cell).  Keeping the x ghosts out of
@@ -40,7 +41,7 @@ struct BlockDev {
                     // across both faces of axis k (periodic, one Block along k);
                     // the sweep then reads across that axis from the Block itself
                     // and no ghost value on that axis is used
-  int pad1;
+  int pack;         // 1: rows packed (Sx = a; rows 2k, 2k + 1 share a line)
 };
 
 // Neighbour entry of a Block for offset class d = 13 + dx + 3 dy + 9 dz:

@@ -93,10 +93,16 @@ __device__ __forceinline__ typename Stor<PREC>::T from_c(C v) {
   else return f32_to_bf16((float)v);
 }
 
-template <typename T, bool NT>
+// Cache policy, measured on gfx950: population loads are ordinary (streaming
+// loads lose 1-6 % on every workload but 32-wide Blocks), and the stores of
+// whole row segments may stream (NT); values written one or a few per row
+// (bounce-back at walls, x-ghost planes) are always ordinary stores, so
+// that the L2 merges the parts of a line that different waves write
+// before it goes to memory (streamed, each such part costs HBM a partial
+// line: 7 % of the FP32 sweep on a 384^3 box with x walls).
+template <typename T>
 __device__ __forceinline__ T ld(const T* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  else return *p;
+  return *p;
 }
 template <typename T, bool NT>
 __device__ __forceinline__ void st(T* p, T v) {
@@ -117,19 +123,19 @@ template <> struct Raw<16> { typedef uint32_t V __attribute__((ext_vector_type(4
 
 // One value at a scalar base plus a 32-bit lane byte offset (one global
 // instruction with the base in SGPRs).
-template <typename T, bool NT>
+template <typename T>
 __device__ __forceinline__ T ldo(const T* base, uint32_t boff) {
-  return ld<T, NT>((const T*)((const char*)base + boff));
+  return ld<T>((const T*)((const char*)base + boff));
 }
 template <typename T, bool NT>
 __device__ __forceinline__ void sto(T* base, uint32_t boff, T v) {
   st<T, NT>((T*)((char*)base + boff), v);
 }
 // VEC consecutive values at a scalar base plus a 32-bit lane byte offset.
-template <typename T, int VEC, bool NT>
+template <typename T, int VEC>
 __device__ __forceinline__ void vld(const T* base, uint32_t boff, T (&out)[VEC]) {
   typedef typename Raw<sizeof(T) * VEC>::V V;
-  const V v = ld<V, NT>((const V*)((const char*)base + boff));
+  const V v = ld<V>((const V*)((const char*)base + boff));
   __builtin_memcpy(out, &v, sizeof(V));
 }
 // One value at base + boff (bytes) by a raw buffer store: the 64-bit base
@@ -162,19 +168,18 @@ constexpr uint32_t kRange = 0xFFFFFFF0u;  // records of a group resource; an off
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t grp_rsrc(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)kRange, 0x00020000);
 }
-template <typename T, bool NT>
+template <typename T>
 __device__ __forceinline__ T rs_load(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  constexpr int aux = NT ? 2 : 0;  // streaming (nt)
   if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, aux));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
   else if constexpr (sizeof(T) == 4)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, aux));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
   else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, aux));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0));
 }
 template <typename T, bool NT>
 __device__ __forceinline__ void rs_store(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T v) {
-  constexpr int aux = NT ? 2 : 0;
+  constexpr int aux = NT ? 2 : 0;  // streaming (nt)
   if constexpr (sizeof(T) == 8)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(unsigned int __attribute__((__vector_size__(8))), v),
                                           rs, voff, soff, aux);
@@ -188,10 +193,10 @@ __device__ __forceinline__ void rs_store(__amdgpu_buffer_rsrc_t rs, uint32_t vof
 // zero-extended) and split later.
 template <int BYTES> struct WideRaw { typedef typename Raw<BYTES>::V V; };
 template <> struct WideRaw<2> { typedef uint32_t V; };
-template <typename T, int VEC, bool NT>
+template <typename T, int VEC>
 __device__ __forceinline__ typename WideRaw<sizeof(T) * VEC>::V ld_wide(const T* base, uint32_t boff) {
   typedef typename Raw<sizeof(T) * VEC>::V V;
-  return (typename WideRaw<sizeof(T) * VEC>::V)ld<V, NT>((const V*)((const char*)base + boff));
+  return (typename WideRaw<sizeof(T) * VEC>::V)ld<V>((const V*)((const char*)base + boff));
 }
 template <typename T, int VEC>
 __device__ __forceinline__ void unpack_wide(typename WideRaw<sizeof(T) * VEC>::V w, T (&out)[VEC]) {
@@ -473,15 +478,15 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
                                        (long long)(y0w + 1) * B.Sx) * (long long)sizeof(T)) + lob + 2u * S1;
       uint32_t o = (i != 0 && ((m[0] >> i) & 1u)) ? own : so + vo;
       o = solid[0] ? kRange : o;
-      W[i][0] = rs_load<T, NT>(rs, o, 0u);
+      W[i][0] = rs_load<T>(rs, o, 0u);
     } else if constexpr (VEC == 1) {
       uint32_t off = lob + (uint32_t)((1 - ex) * (int)sizeof(T));
       if (ex > 0) off = xg_lo ? xlo : off;
       if (ex < 0) off = xg_hi ? xhi : off;
-      W[i][0] = ldo<T, NT>(pr, off);
+      W[i][0] = ldo<T>(pr, off);
     } else {
       T V[VEC];
-      vld<T, VEC, NT>(pr, lob + S1, V);
+      vld<T, VEC>(pr, lob + S1, V);
       // the element just outside the vector: x-ghost slot (or, wrapping, the
       // other end of the row), neighbouring segment, or (interior lanes,
       // replaced by the shuffle) the lane's own
@@ -489,7 +494,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
       if (ex > 0) off = first ? (xg_lo ? xlo : lob) : lob + S1;
       if (ex < 0) off = last ? (xg_hi ? xhi : lob + (uint32_t)(VEC + 1) * S1) : lob + S1;
       T e = V[0];
-      if (ex != 0) e = ldo<T, NT>(pr, off);
+      if (ex != 0) e = ldo<T>(pr, off);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) W[i][k] = V[k];
       if (ex > 0) {
@@ -538,7 +543,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
       bool any = false;
 #pragma unroll
       for (int k = 0; k < VEC; ++k) any = any || ((m[k] >> i) & 1u);
-      if (any) own[i] = ld_wide<T, VEC, NT>(src + (rb + (long long)OPPd(i) * B.Sf), lob);
+      if (any) own[i] = ld_wide<T, VEC>(src + (rb + (long long)OPPd(i) * B.Sf), lob);
     }
 #pragma unroll
     for (int i = 1; i < kQ; ++i) {
@@ -652,12 +657,12 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
         const long long row = B.base + (long long)qb * B.Sf + (long long)(zt + 1) * B.Sz + (long long)(yt + 1) * B.Sx;
         const int j = k + exq;  // target element index relative to x0
         if (!((j < 0 && xg_lo) || (j >= VEC && xg_hi))) {
-          sto<T, NT>(dst + (row - 1), lob + (uint32_t)((j + 1) * (int)sizeof(T)), v);
+          sto<T, false>(dst + (row - 1), lob + (uint32_t)((j + 1) * (int)sizeof(T)), v);
         } else if (wx) {
-          sto<T, NT>(dst + (row - 1), j < 0 ? xwrap_lo : xwrap_hi, v);
+          sto<T, false>(dst + (row - 1), j < 0 ? xwrap_lo : xwrap_hi, v);
         } else {
           const long long dxg = B.xgo + (long long)(zt + 1) * (B.Ry - B.Sz) + (long long)(yt + 1) * (1 - B.Sx) + 1;
-          sto<T, NT>(dst + (row - 1), (uint32_t)((dxg + r) * (long long)sizeof(T)), v);
+          sto<T, false>(dst + (row - 1), (uint32_t)((dxg + r) * (long long)sizeof(T)), v);
         }
       }
     }
@@ -831,7 +836,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
 #pragma unroll
         for (int k = 0; k < VEC; ++k)
           if (nbr_of(q, k) != 13)
-            v[q][k] = ldo<T, false>(dst + (rb + (long long)q * B.Sf), lob + (uint32_t)(k * sizeof(T)));
+            v[q][k] = ldo<T>(dst + (rb + (long long)q * B.Sf), lob + (uint32_t)(k * sizeof(T)));
 #pragma unroll
       for (int q = 1; q < kQ; ++q)
 #pragma unroll

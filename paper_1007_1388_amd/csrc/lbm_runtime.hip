@@ -324,6 +324,7 @@ void build_items(lbm_ctx* c) {
     const BlockDev& B = c->bh[j];
     const int a = B.dim[0], b = B.dim[1], cz = B.dim[2];
     int rows = std::max(1, std::min(b, target / a));
+    if (B.pack) rows = std::max(2, rows & ~1);  // pairs of packed rows share a line
     // The sweep's waves take an item's (row group, 64-lane segment) tasks in
     // turn.  With 16-bit storage, round rows up so that their count is a
     // multiple of the waves per workgroup (a 384-cell row is 6 segments: one
@@ -1175,16 +1176,25 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
       B.org[k] = blocks[j].lo[k];
       B.dim[k] = blocks[j].hi[k] - blocks[j].lo[k];
     }
-    B.Sx = (int)(roundup(B.dim[0], align) + row_pad_lines(*p, B.dim[0] * (long long)c->sbytes) * align);
+    // A row of an odd number of half lines (FP32 rows of 48 cells: 1.5 lines)
+    // padded to whole lines wastes a quarter of the line reads (HBM is read in
+    // 128-byte lines): such rows are packed, two rows to three lines, with row
+    // 0 of every plane on a line (the plane stride a whole number of lines,
+    // the Block's base shifted by half a line); the sweep's items then hold
+    // even numbers of rows, so the two halves of a shared line are written by
+    // waves of one workgroup.  FP32/FP64 storage, even y extents, row_pad 0.
+    B.pack = p->row_pad == 0 && c->prec <= 1 && (B.dim[0] * (long long)c->sbytes) % 128 == 64 && B.dim[1] % 2 == 0;
+    B.Sx = B.pack ? B.dim[0]
+                  : (int)(roundup(B.dim[0], align) + row_pad_lines(*p, B.dim[0] * (long long)c->sbytes) * align);
     B.Ry = B.dim[1] + 2;
-    B.Sz = (long long)B.Sx * (B.dim[1] + 2);
+    B.Sz = roundup((long long)B.Sx * (B.dim[1] + 2), align);
     // array (with y/z ghost layer), one spare row, then its x-ghost plane
     B.xgo = B.Sz * (B.dim[2] + 2) + B.Sx;
     const long long fmin = B.xgo + (long long)B.Ry * (B.dim[2] + 2);
     // stagger the 19 streams so they do not start on the same HBM channel
     B.Sf = roundup(fmin, 4096 / c->sbytes) + 768 / c->sbytes;
-    B.base = off;
-    off = roundup(off + (long long)kQ * B.Sf, 4096 / c->sbytes);
+    B.base = B.pack ? off + (align - B.Sx % align) % align : off;
+    off = roundup(B.base + (long long)kQ * B.Sf, 4096 / c->sbytes);
     B.mask = -1;
   }
   // The sweep addresses a Block's arrays through buffer resources that each

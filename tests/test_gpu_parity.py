@@ -422,6 +422,31 @@ def test_row_padding_is_layout_only(precision):
     assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
 
 
+@pytest.mark.parametrize("precision,dims,split", [("f32", (96, 20, 14), (2, 2, 1)), ("f64", (48, 20, 14), (2, 2, 1)),
+                                                   ("f32", (80, 16, 9), (1, 2, 1))])
+def test_packed_rows_are_layout_only(precision, dims, split):
+    """Rows of an odd number of half lines (FP32 rows of 48 or 80 cells, FP64
+    rows of 24) are packed two to three lines by default (row_pad 0): bitwise
+    equal to rows rounded to whole lines (row_pad -1) and to padded rows, and
+    FP64 against the oracle; obstacles, walls, a body force and a warm start,
+    Blocks of packed and unpacked rows side by side."""
+    solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 3), seed=8)
+    case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7, seed=8)
+    blocks = inputs.uniform_blocks(dims, split)
+    if split == (1, 2, 1):
+        blocks = [((0, 0, 0), (48, 8, 9)), ((48, 0, 0), (80, 8, 9)), ((0, 8, 0), (48, 16, 9)), ((48, 8, 0), (80, 16, 9))]
+    states = []
+    for pad in (0, -1, 2):
+        lat = gpu_lattice(case, blocks=blocks, precision=precision, row_pad=pad)
+        prepare(lat, case)
+        lat.step(19)
+        states.append(lat.get_state(as_fp64=False))
+        if pad == 0 and precision == "f64":
+            check_vs_oracle(lat, run_oracle(case, 19), TOL["f64"])
+        lat.close()
+    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
+
+
 # ------------------------------------------------------ sums, residual ----
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

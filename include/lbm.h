@@ -244,7 +244,8 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64);
 
 /* The schedule in force.  After lbm_create_blocks: fused_exchange = 0 for one
  * Block and 2 for several, item_cells = 512, wg_size = 256, persistent = 0,
- * graph_steps = 0, nontemporal = 1, cells_per_lane = 0. */
+ * graph_steps = 0, nontemporal = 1 (0 for grids of at most 192 MiB, which the
+ * memory-side cache holds from one step to the next), cells_per_lane = 0. */
 lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s);
 /* Validate and apply a schedule (rebuilds the item list and drops captured
  * graphs).  Results do not depend on the schedule, bit for bit. */

@@ -322,9 +322,11 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 
 // One wave updates a row segment: each lane owns VEC consecutive cells of a
 // row, xw lanes per row (the smallest power of two covering the row, at most
-// 64), 64/xw rows per wave, so the plane z and the first row y0w are uniform
-// and every stream is one access at a scalar base (SGPRs) plus a 32-bit lane
-// offset.
+// 64), 64/xw rows per wave, the segment's first cell at x = x0w; or (xw = 0,
+// flat runs, one cell per lane) 64 consecutive cells of the plane, from cell
+// x0w of row y0w on, across row ends.  Either way the plane z and the first
+// row y0w are uniform and every stream is one access at a scalar base (SGPRs)
+// plus a 32-bit lane offset.
 //
 // Pull phase (branch-free, all 19 streams in flight): every population comes
 // from its source slot x - e_i -- inside the Block, from the ghost layer (the
@@ -346,7 +348,7 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 // fused into the sweep).
 template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& ph_in, const void* src_grid, void* dst_grid,
-                                          const BlockDev& B_in, int bid, int z, int y0w, int seg, int yend, int xw,
+                                          const BlockDev& B_in, int bid, int z, int y0w, int x0w, int yend, int xw,
                                           const GhostTgt* gts) {
   // The kernel's arguments (this sweep's pointers, the geometry and the
   // physical constants) are read through the kernel-argument segment at the
@@ -382,9 +384,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   T* __restrict__ dst = (T*)dst_grid;
   const int lane = threadIdx.x & 63;
   const int a = B.dim[0], b = B.dim[1], c = B.dim[2];
-  const int r = lane / xw;
-  const int xl = lane - r * xw;
-  const int x0 = seg * 64 * VEC + xl * VEC;
+  // row of the lane within the wave, its place in the row, its first cell
+  const int r = xw ? lane / xw : (unsigned)(x0w + lane) / (unsigned)a;
+  const int xl = xw ? lane - r * xw : 0;
+  const int x0 = xw ? x0w + xl * VEC : x0w + lane - r * a;
   const int y = y0w + r;
   // Lanes of a live row all take part in the shuffles; a lane only reads a
   // neighbour lane of its own live row.
@@ -682,7 +685,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   // Block only send from their first and last cell, to the two x-face
   // neighbours: their table entries are wave-uniform and read once.  Waves
   // with a row on a y or z face take the generic per-lane path.
-  const int ylast = min(y0w + 64 / xw, yend) - 1;
+  const int ylast = min(y0w + (xw ? 64 / xw : (x0w + 63) / a + 1), yend) - 1;
   const bool yz_face = (z == 0) | (z == c - 1) | (y0w == 0) | (ylast >= b - 1);
   constexpr bool FUSED = FX == 1;
   const bool edge = FUSED && yz_face &&
@@ -872,6 +875,17 @@ __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& p
     }
     const BlockDev B = A.blocks[item.block];
     const int a = B.dim[0];
+    const int yend = item.y0 + item.nrows;
+    if (VEC == 1 && flat_rows(B, VEC, (int)sizeof(typename Stor<PREC>::T)) && ((B.wrap & 2) == 0 || (item.y0 > 0 && yend < B.dim[1]))) {
+      // flat runs: task t covers cells 64 t .. 64 t + 63 of the item
+      const int ntask = (item.nrows * a + 63) >> 6;
+      for (int t = wv; t < ntask; t += nw) {
+        const int f = t * 64, ry = f / a;
+        sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + ry,
+                                                    f - ry * a, yend, 0, gts);
+      }
+      continue;
+    }
     const int lanes = (a + VEC - 1) / VEC;  // lanes per row
     int xw = 64;
     while (xw > 1 && xw / 2 >= lanes) xw >>= 1;
@@ -879,11 +893,10 @@ __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& p
     const int nseg = (lanes + 63) >> 6;           // 64-lane segments per row
     const int ngroups = (item.nrows + rpw - 1) / rpw;
     const int ntask = ngroups * nseg;
-    const int yend = item.y0 + item.nrows;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + grp * rpw, seg,
-                                                  yend, xw, gts);
+      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + grp * rpw,
+                                                  seg * 64 * VEC, yend, xw, gts);
     }
   }
 }

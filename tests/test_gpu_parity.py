@@ -425,11 +425,13 @@ def test_row_padding_is_layout_only(precision):
 @pytest.mark.parametrize("precision,dims,split", [("f32", (96, 20, 14), (2, 2, 1)), ("f64", (48, 20, 14), (2, 2, 1)),
                                                    ("f32", (80, 16, 9), (1, 2, 1))])
 def test_packed_rows_are_layout_only(precision, dims, split):
-    """Rows of an odd number of half lines (FP32 rows of 48 or 80 cells, FP64
-    rows of 24) are packed two to three lines by default (row_pad 0): bitwise
-    equal to rows rounded to whole lines (row_pad -1) and to padded rows, and
-    FP64 against the oracle; obstacles, walls, a body force and a warm start,
-    Blocks of packed and unpacked rows side by side."""
+    """Rows of an odd number of half lines (FP32 rows of 48 or 80 cells) are
+    packed two to three lines by default (row_pad 0), and rows stored back to
+    back (packed, or FP32 96 and FP64 48 cells) run as flat runs of 64 cells
+    across row ends: bitwise equal to rows rounded to whole lines (row_pad -1)
+    and to padded rows (row segments), and FP64 against the oracle; obstacles,
+    walls, a body force and a warm start, Blocks of packed and unpacked rows
+    side by side."""
     solid = inputs.porous_spheres(dims, target_fraction=0.1, radius=(1, 3), seed=8)
     case = channel(dims=dims, solid=solid, force=(2e-5, 0, 0), tau=0.7, seed=8)
     blocks = inputs.uniform_blocks(dims, split)

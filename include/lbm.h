@@ -61,8 +61,9 @@ typedef enum {
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_precision;
 
 /* Face kinds.  PERIODIC faces come in opposite pairs.  VELOCITY and
- * PRESSURE are open faces (x faces only): the boundary node one cell beyond
- * the face, next to the domain cell x_f, holds the post-collision
+ * PRESSURE are open faces, on the faces of one axis (x, y or z; the other
+ * face of that axis open or WALL): the boundary node one cell beyond the
+ * face, next to the domain cell x_f, holds the post-collision
  * populations of the non-equilibrium extrapolation rule (Guo, Zheng and Shi,
  * 2002; on-GPU boundary conditions are the paper's stated future work,
  * Sec. 5.1 and the conclusion):
@@ -71,10 +72,10 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_preci
  * prescribes u_b = wall_u[face] and takes drho_b = drho_f; PRESSURE
  * prescribes rho_b = face_rho[face] and takes u_b = u_f.  A link whose
  * source lies beyond a WALL face as well bounces back (walls take
- * precedence).  Open faces need nx >= 2 and no solid cell on the face; the
- * Blocks may be cut across y and z (a boundary node feeds the face cells of
- * the Blocks next to it through their ghost rows); their contexts run one
- * cell per lane. */
+ * precedence).  Open faces need two or more cells across them and no solid
+ * cell on the face; the Blocks may be cut along and across the open axis (a
+ * boundary node feeds the face cells of the Blocks next to it through their
+ * ghost cells).  Contexts with open x faces run one cell per lane. */
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_VELOCITY = 2, LBM_PRESSURE = 3 } lbm_face;
 
 /* Half-open global cell box [lo, hi) of one Block (the Block AABB, Sec. 4.2). */
@@ -127,7 +128,7 @@ typedef struct {
                               planes) are ordinary either way.  Results do not depend on it. */
   int32_t cells_per_lane;  /* cells per lane along x: 0 = automatic (1); 1; or 2 (only for
                               F16S/BF16S and for F32 storage with FP64 arithmetic, with
-                              every Block's x extent even and no open face, else
+                              every Block's x extent even and no open x face, else
                               LBM_EINVAL).  Results do not depend on it. */
 } lbm_schedule;
 
@@ -241,6 +242,23 @@ lbm_status lbm_get_state(lbm_ctx* c, void* f, int32_t as_fp64);
  * at 0).  The state is taken as post-collision; the step counter is reset to
  * 1 so that lbm_macroscopic reports its moments with the half-force shift. */
 lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64);
+
+/* Replace the state by the mean of the last two post-collision states (this
+ * step's and the previous step's, which the two grids hold), value by value
+ * in the storage format; ghost layers, wall slots and open-face boundary
+ * nodes are then rebuilt from the mean.  Every part of the state that flips
+ * sign from one step to the next cancels; the rest moves half a step back.
+ * For starts from a state set from outside (the learned warm start sets an
+ * equilibrium of predicted fields, Sec. 2.1's f^eq): such a state excites
+ * period-two components that a few pore geometries hardly damp, so the
+ * velocity keeps a step-to-step oscillation for tens of thousands of steps
+ * while its two-step mean has converged.  One call after the first step
+ * removes them.  Not an operation of the paper's method.
+ * LBM_ESTATE without a step since the state was last set (creation,
+ * lbm_set_geometry, lbm_set_equilibrium, lbm_set_state or this call);
+ * LBM_EINVAL with host Blocks.  The step count is kept; lbm_residual needs
+ * one more step.  Synchronises. */
+lbm_status lbm_average_two_steps(lbm_ctx* c);
 
 /* The schedule in force.  After lbm_create_blocks: fused_exchange = 0 for one
  * Block and 2 for several, item_cells = 512, wg_size = 256, persistent = 0,

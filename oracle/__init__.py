@@ -66,8 +66,8 @@ def _load():
         lib.orc_velocity.argtypes = [ctypes.c_int, ip]
         lib.orc_weight.argtypes = [ctypes.c_int]
         lib.orc_weight.restype = ctypes.c_double
-        lib.orc_set_xface.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double]
-        lib.orc_set_xface.restype = ctypes.c_int
+        lib.orc_set_face.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double]
+        lib.orc_set_face.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -81,13 +81,14 @@ class OracleLBM:
 
     dims = (nx, ny, nz); walls = per-axis flag (True: half-way bounce-back
     walls on both faces, False: periodic); wall_u = {face: (ux, uy, uz)};
-    open_x = {"-x" or "+x": ("velocity", (ux, uy, uz)) | ("pressure", rho) |
-    "wall"}: open x faces by non-equilibrium extrapolation (a face not named
-    keeps what `walls` says; x must not be periodic then).
+    open_faces = {face: ("velocity", (ux, uy, uz)) | ("pressure", rho) |
+    "wall"}, faces of one axis ("-x"/"+x", "-y"/"+y" or "-z"/"+z"): open faces
+    by non-equilibrium extrapolation (a face not named keeps what `walls`
+    says; that axis must not be periodic then).  open_x is the older name.
     """
 
     def __init__(self, dims, walls=(False, False, False), wall_u=None, tau=0.6,
-                 rho0=1.0, force=(0.0, 0.0, 0.0), open_x=None):
+                 rho0=1.0, force=(0.0, 0.0, 0.0), open_x=None, open_faces=None):
         lib = _load()
         self.dims = tuple(int(d) for d in dims)
         self.rho0 = float(rho0)
@@ -103,8 +104,8 @@ class OracleLBM:
         if not self._h:
             raise ValueError("oracle: invalid parameters")
         self._lib = lib
-        for face, spec in (open_x or {}).items():
-            side = {"-x": 0, "+x": 1}[face]
+        for face, spec in dict(open_x or {}, **(open_faces or {})).items():
+            side = FACES.index(face)
             if spec == "wall":
                 kind, u, rho = 1, np.zeros(3), 0.0
             elif spec[0] == "velocity":
@@ -113,7 +114,7 @@ class OracleLBM:
                 kind, u, rho = 3, np.zeros(3), float(spec[1])
             else:
                 raise ValueError("oracle: bad open face %r" % (spec,))
-            if lib.orc_set_xface(self._h, side, kind, _dptr(u), rho) != 0:
+            if lib.orc_set_face(self._h, side, kind, _dptr(u), rho) != 0:
                 raise ValueError("oracle: bad open face")
         nx, ny, nz = self.dims
         self.shape = (nz, ny, nx)

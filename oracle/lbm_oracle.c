@@ -30,13 +30,15 @@
  *             g'_i(x) = f_i - (1/tau)(f_i - feq~_i) + (1 - 1/(2 tau)) F_i.
  *   Solid cells are never updated and always hold 0; they report rho0 and 0.
  *
- * Open x faces (an extension: the paper names boundary conditions computed
- * on the GPU as future work, Sec. 5.1 and the conclusion): a VELOCITY or
- * PRESSURE face replaces the wall or the periodic image by a boundary node
- * one cell outside, whose post-collision populations follow the
- * non-equilibrium extrapolation rule of Guo, Zheng and Shi (2002):
+ * Open faces (an extension: the paper names boundary conditions computed
+ * on the GPU as future work, Sec. 5.1 and the conclusion), on the two faces
+ * of one axis: a VELOCITY or PRESSURE face replaces the wall or the periodic
+ * image by a boundary node one cell outside, whose post-collision
+ * populations follow the non-equilibrium extrapolation rule of Guo, Zheng
+ * and Shi (2002):
  *     g_i(x_b) = feq~_i(drho_b, u_b) + [ g_i(x_f) - feq~_i(drho_f, u_f) ],
- * x_f the domain cell next to x_b (same y, z), drho_f and u_f the moments of
+ * x_f the domain cell next to x_b (the same position along the two other
+ * axes, wrapped on a periodic one), drho_f and u_f the moments of
  * x_f rebuilt from its post-collision populations (drho = sum g,
  * u = sum e g / rho0 - g/2: the collision keeps drho and adds rho0 g to the
  * momentum).  A velocity face prescribes u_b and takes drho_b = drho_f; a
@@ -83,8 +85,8 @@ typedef struct {
     int n[3];          /* nx, ny, nz */
     int wall[3];       /* per axis: 0 periodic, 1 half-way bounce-back walls */
     int kind[6];       /* per face -x,+x,-y,+y,-z,+z: ORC_* */
-    double ob_u[2][3]; /* prescribed velocity of an open -x / +x face */
-    double ob_rho[2];  /* prescribed density of an open -x / +x face */
+    double ob_u[6][3]; /* prescribed velocity of an open face */
+    double ob_rho[6];  /* prescribed density of an open face */
     double uw[6][3];   /* wall velocity of faces -x,+x,-y,+y,-z,+z */
     double tau, rho0;
     double g[3];       /* body force per unit mass, lattice units */
@@ -170,17 +172,27 @@ orc_lbm *orc_create(const int *dims, const int *wall_axis, const double *wall_u,
     return L;
 }
 
-/* Make x face `side` (0: -x, 1: +x) open: kind ORC_VELOCITY with velocity
- * u[3], or ORC_PRESSURE with density rho; ORC_WALL or ORC_PERIODIC restore
- * those (a periodic x needs both faces periodic).  Returns 0, or -1 on a bad
- * argument. */
-int orc_set_xface(orc_lbm *L, int side, int kind, const double *u, double rho) {
-    if (side < 0 || side > 1 || kind < ORC_PERIODIC || kind > ORC_PRESSURE) return -1;
-    L->kind[side] = kind;
-    for (int a = 0; a < 3; ++a) L->ob_u[side][a] = (kind == ORC_VELOCITY && u) ? u[a] : 0.0;
-    L->ob_rho[side] = kind == ORC_PRESSURE ? rho : L->rho0;
-    L->wall[0] = L->kind[0] != ORC_PERIODIC || L->kind[1] != ORC_PERIODIC;
+/* Make face `face` (0..5: -x, +x, -y, +y, -z, +z) open: kind ORC_VELOCITY
+ * with velocity u[3], or ORC_PRESSURE with density rho; ORC_WALL or
+ * ORC_PERIODIC restore those (a periodic axis needs both faces periodic).
+ * Open faces lie on one axis only.  Returns 0, or -1 on a bad argument. */
+int orc_set_face(orc_lbm *L, int face, int kind, const double *u, double rho) {
+    if (face < 0 || face > 5 || kind < ORC_PERIODIC || kind > ORC_PRESSURE) return -1;
+    if (kind == ORC_VELOCITY || kind == ORC_PRESSURE)
+        for (int f = 0; f < 6; ++f)
+            if (f / 2 != face / 2 && (L->kind[f] == ORC_VELOCITY || L->kind[f] == ORC_PRESSURE)) return -1;
+    L->kind[face] = kind;
+    for (int a = 0; a < 3; ++a) L->ob_u[face][a] = (kind == ORC_VELOCITY && u) ? u[a] : 0.0;
+    L->ob_rho[face] = kind == ORC_PRESSURE ? rho : L->rho0;
+    const int a = face / 2;
+    L->wall[a] = L->kind[2 * a] != ORC_PERIODIC || L->kind[2 * a + 1] != ORC_PERIODIC;
     return 0;
+}
+
+/* The same for the x faces (side 0: -x, 1: +x). */
+int orc_set_xface(orc_lbm *L, int side, int kind, const double *u, double rho) {
+    if (side < 0 || side > 1) return -1;
+    return orc_set_face(L, side, kind, u, rho);
 }
 
 /* Solid mask [z][y][x] (1 = solid), NULL = all fluid; resets to rest. */
@@ -214,7 +226,7 @@ void orc_set_equilibrium(orc_lbm *L, const double *rho, const double *u) {
     L->steps = 0;
 }
 
-/* Post-collision population i of the boundary node one cell beyond open x
+/* Post-collision population i of the boundary node one cell beyond open
  * face `side`, next to the domain cell xf (non-equilibrium extrapolation,
  * see the file header). */
 static double open_node(const orc_lbm *L, int side, int i, size_t xf) {
@@ -258,14 +270,15 @@ static void update_cell(orc_lbm *L, int x, int y, int z) {
                 } else if (L->kind[face] == ORC_PERIODIC) {
                     s[a] = (s[a] + L->n[a]) % L->n[a]; /* periodic image */
                 } else {
-                    ofc = face; /* only x faces are open */
+                    ofc = face; /* open faces lie on one axis */
                 }
             }
         }
         if (!wall_link && ofc >= 0) {
             /* boundary node beyond an open face; x_f next to it inside */
-            const int xf = ofc == 0 ? 0 : L->n[0] - 1;
-            f[i] = open_node(L, ofc, i, cidx(L, xf, s[1], s[2]));
+            int q[3] = {s[0], s[1], s[2]};
+            q[ofc / 2] = ofc % 2 == 0 ? 0 : L->n[ofc / 2] - 1;
+            f[i] = open_node(L, ofc, i, cidx(L, q[0], q[1], q[2]));
             continue;
         }
         if (!wall_link && L->solid[cidx(L, s[0], s[1], s[2])]) {

@@ -98,9 +98,10 @@ struct GridGeom {
   int wall[3];      // 1: the axis is bounded (walls or open faces), 0: periodic
   int fwall[6];     // face is a bounce-back wall
   int moving[6];    // wall face with a nonzero wall velocity
-  int open[2];      // -x / +x face: 0 not open, 1 VELOCITY, 2 PRESSURE
-  double ob_u[2][3];  // prescribed velocity of an open face
-  double ob_drho[2];  // prescribed rho - rho0 of an open face
+  int open[6];      // face -x, +x, -y, +y, -z, +z: 0 not open, 1 VELOCITY, 2 PRESSURE
+  int open_axis;    // axis of the open faces (they lie on one axis), -1: none
+  double ob_u[6][3];  // prescribed velocity of an open face
+  double ob_drho[6];  // prescribed rho - rho0 of an open face
   double rho0;        // reference density and g/2 (open faces rebuild the
   double hg[3];       // velocity of a post-collision state)
 };

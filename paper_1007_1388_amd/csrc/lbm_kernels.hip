@@ -1100,91 +1100,129 @@ __global__ void __launch_bounds__(256) k_bbfill(void* grid_, CellArgs A, const P
   });
 }
 
-// Open x faces, once per step after the sweep (and after a state is loaded,
-// from k_openside): the boundary nodes beyond the open faces from the face
-// cells' moments and entering populations in `side` (the moments of their
-// collision, as the boundary rule asks).  A boundary node at (-1 or nx, y, z)
-// feeds the face cells around (y, z), so its value goes into the x-ghost
-// plane of every face Block whose plane, ghost rows included, covers (y, z):
-// the Block that owns the face cell and the face Blocks next to it across y
-// or z (and, on a periodic axis, the Blocks holding its periodic image in
-// their ghost rows).  One thread per node position (y, z) in [-1, ny] x
-// [-1, nz] of each face; nodes beyond a wall are left to the sweep's
-// bounce-back.  faceblk: per face the count of Blocks touching it, then
-// their ids (stride 1 + nblocks).
+// Open faces (on one axis a; t1 < t2 the two other axes).  The side buffer
+// holds, per face (low, high) and face cell (s1, s2) at [face][s2][s1], 16
+// doubles: the post-collision populations of the five directions that enter
+// the domain through the face (slot k: the k-th direction i in increasing
+// order with e_a(i) = +1 on the low face, -1 on the high face), then
+// drho, u_x, u_y, u_z of the cell's collision, then zeros (one 128-byte line
+// per cell).
+__device__ __forceinline__ int ecomp(int axis, int i) { return axis == 0 ? kEx[i] : (axis == 1 ? kEy[i] : kEz[i]); }
+__device__ __forceinline__ int enter_dir(int axis, int sign, int slot) {
+  int k = 0;
+  for (int i = 1; i < kQ; ++i)
+    if (ecomp(axis, i) == sign) {
+      if (k == slot) return i;
+      ++k;
+    }
+  return 0;
+}
+__device__ __forceinline__ void tangential(int a, int& t1, int& t2) {
+  t1 = a == 0 ? 1 : 0;
+  t2 = a == 2 ? 1 : 2;
+}
+
+// Once per step after the sweep (and after a state is loaded): the boundary
+// nodes beyond the open faces from the face cells' entries in `side` (the
+// moments of their collision, as the boundary rule asks).  A boundary node
+// one cell beyond face f at tangential position (g1, g2) feeds the face
+// cells around it, so its value goes into the ghost layer of every Block on
+// that face whose ghost layer, tangential ghost cells included, covers it:
+// the Block that owns the face cell, the face Blocks next to it, and on a
+// periodic tangential axis the Blocks that hold its periodic image.  In a
+// Block the node lies in the main arrays' ghost rows (y faces) or planes
+// (z faces) or, for x faces and past a Block's x ends, in the x-ghost plane
+// of the directions that pull from there.  One thread per node position
+// (g1, g2) in [-1, n1] x [-1, n2] of each face; nodes beyond a wall are left
+// to the sweep's bounce-back.  faceblk: per face the count of Blocks
+// touching it, then their ids (stride 1 + nblocks).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_openfill(void* grid_, const BlockDev* __restrict__ blocks, int nblocks,
                                                   const int* __restrict__ faceblk, GridGeom geo,
                                                   const double* __restrict__ side) {
   using T = typename Stor<PREC>::T;
   T* grid = (T*)grid_;
-  const int ny = geo.n[1], nz = geo.n[2];
-  const int per_face = (ny + 2) * (nz + 2);
+  const int a = geo.open_axis;
+  int t1, t2;
+  tangential(a, t1, t2);
+  const int n1 = geo.n[t1], n2 = geo.n[t2];
+  const int per_face = (n1 + 2) * (n2 + 2);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * per_face) return;
-  const int f = t / per_face, yz = t % per_face;
+  if (a < 0 || t >= 2 * per_face) return;
+  const int fs = t / per_face, r = t % per_face;
+  const int f = 2 * a + fs;
   if (!geo.open[f]) return;
-  const int gy = yz % (ny + 2) - 1, gz = yz / (ny + 2) - 1;
-  if ((gy < 0 || gy >= ny) && geo.wall[1]) return;
-  if ((gz < 0 || gz >= nz) && geo.wall[2]) return;
-  const int sy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-  const int sz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);
-  const double* cs = side + 16 * ((long long)f * ny * nz + (long long)sz * ny + sy);
+  const int g1 = r % (n1 + 2) - 1, g2 = r / (n1 + 2) - 1;
+  if ((g1 < 0 || g1 >= n1) && geo.wall[t1]) return;
+  if ((g2 < 0 || g2 >= n2) && geo.wall[t2]) return;
+  const int s1 = g1 < 0 ? g1 + n1 : (g1 >= n1 ? g1 - n1 : g1);
+  const int s2 = g2 < 0 ? g2 + n2 : (g2 >= n2 ? g2 - n2 : g2);
+  const double* cs = side + 16 * ((long long)fs * n1 * n2 + (long long)s2 * n1 + s1);
   const double d = cs[5], ux = cs[6], uy = cs[7], uz = cs[8];
+  const int sign = fs == 0 ? 1 : -1;
   T v[5];
   for (int slot = 0; slot < 5; ++slot) {
-    const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
+    const int q = enter_dir(a, sign, slot);
     v[slot] = from_c<PREC, double>(cs[slot] + open_corr(geo, f, q, geo.rho0, d, ux, uy, uz));
   }
-  const int* list = faceblk + f * (1 + nblocks);
+  const int* list = faceblk + fs * (1 + nblocks);
   for (int k = 0; k < list[0]; ++k) {
     const BlockDev& M = blocks[list[1 + k]];
-    const int ly = gy - M.org[1], lz = gz - M.org[2];
-    if (ly < -1 || ly > M.dim[1] || lz < -1 || lz > M.dim[2]) continue;
+    int l[3];
+    l[a] = fs == 0 ? -1 : M.dim[a];
+    l[t1] = g1 - M.org[t1];
+    l[t2] = g2 - M.org[t2];
+    if (l[t1] < -1 || l[t1] > M.dim[t1] || l[t2] < -1 || l[t2] > M.dim[t2]) continue;
     for (int slot = 0; slot < 5; ++slot) {
-      const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
-      grid[xg_off(M, q, ly, lz)] = v[slot];
+      const int q = enter_dir(a, sign, slot);
+      if (l[0] >= 0 && l[0] < M.dim[0])
+        grid[main_off(M, q, l[0], l[1], l[2])] = v[slot];
+      else if ((l[0] < 0 && kEx[q] == 1) || (l[0] >= M.dim[0] && kEx[q] == -1))
+        grid[xg_off(M, q, l[1], l[2])] = v[slot];
     }
   }
 }
 
-// After a state is loaded (rest state, warm start, checkpoint): the face
-// cells' entries of `side` rebuilt from their stored post-collision
+// The face cells' entries of `side` rebuilt from their stored post-collision
 // populations (drho = sum f~, u = sum e f~ / rho0 - g/2: the collision
-// invariants, so the moments of their last collision up to rounding), in the
-// layout the sweep writes, for k_openfill.  One thread per face cell (FP64).
+// invariants, so the moments of their last collision up to rounding): after
+// every sweep for y and z faces, after a state is loaded for x faces (whose
+// entries the sweep writes itself).  One thread per face cell (FP64).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_openside(const void* grid_, const BlockDev* __restrict__ blocks,
                                                   int nblocks, const int* __restrict__ faceblk, GridGeom geo,
                                                   double* __restrict__ side) {
   using T = typename Stor<PREC>::T;
   const T* grid = (const T*)grid_;
-  const int ny = geo.n[1], nz = geo.n[2];
-  const int per_face = ny * nz;
+  const int a = geo.open_axis;
+  int t1, t2;
+  tangential(a, t1, t2);
+  const int n1 = geo.n[t1], n2 = geo.n[t2];
+  const int per_face = n1 * n2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * per_face) return;
-  const int f = t / per_face, yz = t % per_face;
-  if (!geo.open[f]) return;
-  const int gy = yz % ny, gz = yz / ny;
-  const int* list = faceblk + f * (1 + nblocks);
+  if (a < 0 || t >= 2 * per_face) return;
+  const int fs = t / per_face, r = t % per_face;
+  if (!geo.open[2 * a + fs]) return;
+  const int g1 = r % n1, g2 = r / n1;
+  const int sign = fs == 0 ? 1 : -1;
+  const int* list = faceblk + fs * (1 + nblocks);
   for (int k = 0; k < list[0]; ++k) {
     const BlockDev& B = blocks[list[1 + k]];
-    const int y = gy - B.org[1], z = gz - B.org[2];
-    if (y < 0 || y >= B.dim[1] || z < 0 || z >= B.dim[2]) continue;
-    const int x = f == 0 ? 0 : B.dim[0] - 1;
+    int l[3];
+    l[a] = fs == 0 ? 0 : B.dim[a] - 1;
+    l[t1] = g1 - B.org[t1];
+    l[t2] = g2 - B.org[t2];
+    if (l[t1] < 0 || l[t1] >= B.dim[t1] || l[t2] < 0 || l[t2] >= B.dim[t2]) continue;
     double fi[kQ], dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
     for (int i = 0; i < kQ; ++i) {
-      fi[i] = (double)to_c<PREC, double>(grid[main_off(B, i, x, y, z)]);
+      fi[i] = (double)to_c<PREC, double>(grid[main_off(B, i, l[0], l[1], l[2])]);
       dr += fi[i];
       jx += EXd(i) * fi[i];
       jy += EYd(i) * fi[i];
       jz += EZd(i) * fi[i];
     }
-    double* cs = side + 16 * ((long long)f * per_face + yz);
-    for (int slot = 0; slot < 5; ++slot) {
-      const int q = f == 0 ? (slot == 0 ? 1 : 5 + 2 * slot) : (slot == 0 ? 2 : 6 + 2 * slot);
-      cs[slot] = fi[q];
-    }
+    double* cs = side + 16 * ((long long)fs * per_face + r);
+    for (int slot = 0; slot < 5; ++slot) cs[slot] = fi[enter_dir(a, sign, slot)];
     cs[5] = dr;
     cs[6] = jx / geo.rho0 - geo.hg[0];
     cs[7] = jy / geo.rho0 - geo.hg[1];
@@ -1356,6 +1394,20 @@ __global__ void __launch_bounds__(256) k_set_state(void* grid_, CellArgs A, cons
   });
 }
 
+// Mean of the two grids' stored values, written into `cur` (every element:
+// main arrays, ghost layers and slots; the caller rebuilds ghosts and slots
+// from the mean).  Storage stays shifted (the mean of shifted values is the
+// shifted mean); 16-bit values are averaged in FP32 and rounded once.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_average(void* cur_, const void* prev_, long long n) {
+  using T = typename Stor<PREC>::T;
+  using A = typename std::conditional<PREC == 0, double, float>::type;
+  T* cur = (T*)cur_;
+  const T* prev = (const T*)prev_;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    cur[k] = from_c<PREC, A>((to_c<PREC, A>(cur[k]) + to_c<PREC, A>(prev[k])) * (A)0.5);
+}
+
 // Attainable-bandwidth probe: 16-byte vector copy (Sec. 3.1 measures the
 // device's copy bandwidth the same way).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -1515,9 +1567,18 @@ void launch_bbfill(int prec, bool f64math, void* grid, const CellArgs& a, const 
   }
 }
 
+// node positions (openfill) or face cells (openside) of both open faces
+static int open_threads(const GridGeom& geo, int ghost) {
+  const int a = geo.open_axis;
+  if (a < 0) return 0;
+  const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+  return 2 * (geo.n[t1] + 2 * ghost) * (geo.n[t2] + 2 * ghost);
+}
+
 void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
                      const GridGeom& geo, const double* side, hipStream_t s) {
-  const int n = 2 * (geo.n[1] + 2) * (geo.n[2] + 2);
+  const int n = open_threads(geo, 1);
+  if (n == 0) return;
   const dim3 g((n + 255) / 256), b(256);
   switch (prec) {
     case 0: hipLaunchKernelGGL(k_openfill<0>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
@@ -1529,7 +1590,8 @@ void launch_openfill(int prec, void* grid, const BlockDev* blocks, int nblocks, 
 
 void launch_openside(int prec, const void* grid, const BlockDev* blocks, int nblocks, const int* faceblk,
                      const GridGeom& geo, double* side, hipStream_t s) {
-  const int n = 2 * geo.n[1] * geo.n[2];
+  const int n = open_threads(geo, 0);
+  if (n == 0) return;
   const dim3 g((n + 255) / 256), b(256);
   switch (prec) {
     case 0: hipLaunchKernelGGL(k_openside<0>, g, b, 0, s, grid, blocks, nblocks, faceblk, geo, side); break;
@@ -1590,6 +1652,17 @@ void launch_get_state(int prec, bool f64, const void* grid, const CellArgs& a, v
     case 5: hipLaunchKernelGGL((k_get_state<2, true>), g, b, 0, s, grid, a, out, N); break;
     case 6: hipLaunchKernelGGL((k_get_state<3, false>), g, b, 0, s, grid, a, out, N); break;
     default: hipLaunchKernelGGL((k_get_state<3, true>), g, b, 0, s, grid, a, out, N); break;
+  }
+}
+
+void launch_average(int prec, void* cur, const void* prev, long long n, hipStream_t s) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  dim3 g((unsigned)std::max<long long>(1, blocks)), b(256);
+  switch (prec) {
+    case 0: hipLaunchKernelGGL(k_average<0>, g, b, 0, s, cur, prev, n); break;
+    case 1: hipLaunchKernelGGL(k_average<1>, g, b, 0, s, cur, prev, n); break;
+    case 2: hipLaunchKernelGGL(k_average<2>, g, b, 0, s, cur, prev, n); break;
+    default: hipLaunchKernelGGL(k_average<3>, g, b, 0, s, cur, prev, n); break;
   }
 }
 

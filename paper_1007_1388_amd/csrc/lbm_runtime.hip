@@ -51,6 +51,7 @@ void launch_get_state(int prec, bool f64, const void* grid, const CellArgs& a, v
 void launch_set_state(int prec, bool f64, void* grid, const CellArgs& a, const void* in, long long N,
                       hipStream_t s);
 void launch_copy16(const void* src, void* dst, long long n16, int grid, hipStream_t s);
+void launch_average(int prec, void* cur, const void* prev, long long n, hipStream_t s);
 void launch_exchange_buf(int prec, int mode, void* grid, const BlockDev* blocks, const NbrDev* nbr,
                          const XchgTask* tasks, int ntasks, void* buf, hipStream_t s);
 }  // namespace lbm
@@ -126,11 +127,12 @@ struct lbm_ctx {
   double* d_partial = nullptr;
   int nparts = 1024;
   double* d_red = nullptr;
-  double* d_side = nullptr;  // open x faces: [face][nz][ny][16] (see SweepArgs::side)
-  int* d_faceblk = nullptr;  // open x faces: per face the count of Blocks touching it, then their ids
+  double* d_side = nullptr;  // open faces: [face][s2][s1][16] over the two other axes (see k_openfill)
+  int* d_faceblk = nullptr;  // open faces: per face the count of Blocks touching it, then their ids
   void* d_stage = nullptr;
   double* d_umark = nullptr;   // [rho | u_x | u_y | u_z] snapshot, FP64, 4 N
   long long mark_steps = -1;   // step count of the snapshot, -1 = none
+  long long set_steps = 0;     // step count when the state was last written from outside the sweep
   size_t stage_bytes = 0;
 
   int cur = 0;
@@ -468,7 +470,9 @@ SweepArgs sweep_args(const lbm_ctx* c, int from) {
   a.items = c->d_items;
   a.mask = c->d_mask;
   a.ghost = c->d_ghost;
-  a.side = c->d_side;
+  // the sweep writes the side entries of open x faces itself (y and z faces:
+  // k_openside after the sweep)
+  a.side = c->geo.open_axis == 0 ? c->d_side : nullptr;
   a.nitems = (int)c->items_h.size();
   a.geo = c->geo;
   if (hetero(c)) {
@@ -535,7 +539,8 @@ void enqueue_fill(lbm_ctx* c, int g, hipStream_t s) {
 // a single cell per lane the sweep keeps more waves resident and measured
 // faster for every storage mode on gfx950).
 // Two cells per lane: F16S/BF16S or F32 with FP64 math, even x extents, and
-// no open faces (the sweep keeps one face cell per lane for them).
+// no open x faces (the sweep keeps one face cell per lane for them; open y
+// or z faces leave the sweep untouched).
 bool vec2_allowed(const lbm_ctx* c) {
   return c->x_even && sweep_vec2_ok(c->prec, c->f64math) && !c->geo.open[0] && !c->geo.open[1];
 }
@@ -553,14 +558,18 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
                cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 
-bool has_open(const lbm_ctx* c) { return c->geo.open[0] || c->geo.open[1]; }
+bool has_open(const lbm_ctx* c) { return c->geo.open_axis >= 0; }
 
 // After the sweep into grid g: the ghost exchange (unless the sweep did it)
 // and the boundary nodes of open faces.
 void enqueue_post(lbm_ctx* c, int g, hipStream_t s) {
   if (c->sched.fused_exchange != 1) enqueue_exchange(c, g, s, c->sched.fused_exchange == 2);
-  if (has_open(c))
-    launch_openfill(c->prec, c->grid[g], c->d_blocks, (int)c->bh.size(), c->d_faceblk, c->geo, c->d_side, s);
+  if (has_open(c)) {
+    const int nb = (int)c->bh.size();
+    if (c->geo.open_axis != 0)
+      launch_openside(c->prec, c->grid[g], c->d_blocks, nb, c->d_faceblk, c->geo, c->d_side, s);
+    launch_openfill(c->prec, c->grid[g], c->d_blocks, nb, c->d_faceblk, c->geo, c->d_side, s);
+  }
 }
 
 void enqueue_step(lbm_ctx* c, int from, hipStream_t s) {
@@ -1039,15 +1048,17 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
   if (p->precision < LBM_F64 || p->precision > LBM_BF16S) return fail(LBM_EINVAL, "bad precision");
   if (p->row_pad < -1 || p->row_pad > 64) return fail(LBM_EINVAL, "row_pad must be in [-1, 64]");
-  bool any_open = false;
+  int open_axis = -1;
   for (int k = 0; k < 3; ++k) {
     if (!std::isfinite(p->force[k])) return fail(LBM_EINVAL, "force must be finite");
     const int f0 = p->face[2 * k], f1 = p->face[2 * k + 1];
     for (const int fk : {f0, f1}) {
       if (fk < LBM_PERIODIC || fk > LBM_PRESSURE) return fail(LBM_EINVAL, "bad face kind");
-      if ((fk == LBM_VELOCITY || fk == LBM_PRESSURE) && k != 0)
-        return fail(LBM_EINVAL, "VELOCITY and PRESSURE faces are x faces only");
-      any_open = any_open || fk == LBM_VELOCITY || fk == LBM_PRESSURE;
+      if (fk == LBM_VELOCITY || fk == LBM_PRESSURE) {
+        if (open_axis >= 0 && open_axis != k)
+          return fail(LBM_EINVAL, "VELOCITY and PRESSURE faces lie on one axis");
+        open_axis = k;
+      }
     }
     if ((f0 == LBM_PERIODIC) != (f1 == LBM_PERIODIC))
       return fail(LBM_EINVAL, "PERIODIC faces come in opposite pairs");
@@ -1066,7 +1077,8 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   std::vector<int> cuts[3], owner;
   std::string err;
   if (!build_tiling(p->dims, blocks, nblocks, cuts, owner, err)) return fail(LBM_EINVAL, err);
-  if (any_open && p->dims[0] < 2) return fail(LBM_EINVAL, "open x faces need nx >= 2");
+  if (open_axis >= 0 && p->dims[open_axis] < 2)
+    return fail(LBM_EINVAL, "open faces need at least two cells across them");
 
   lbm_ctx* c = new lbm_ctx();
   c->p = *p;
@@ -1101,7 +1113,8 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   }
   c->geo.rho0 = p->rho0;
   for (int k = 0; k < 3; ++k) c->geo.hg[k] = 0.5 * p->force[k];
-  for (int s = 0; s < 2; ++s) {
+  c->geo.open_axis = open_axis;
+  for (int s = 0; s < 6; ++s) {
     c->geo.open[s] = p->face[s] == LBM_VELOCITY ? 1 : (p->face[s] == LBM_PRESSURE ? 2 : 0);
     for (int k = 0; k < 3; ++k) c->geo.ob_u[s][k] = p->face[s] == LBM_VELOCITY ? p->wall_u[s][k] : 0.0;
     c->geo.ob_drho[s] = p->face[s] == LBM_PRESSURE ? p->face_rho[s] - p->rho0 : 0.0;
@@ -1306,11 +1319,13 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
   c->d_rim = (XchgTask*)dalloc(c, sizeof(XchgTask) * std::max<size_t>(1, c->rim_h.size()));
   c->d_partial = (double*)dalloc(c, sizeof(double) * 6 * c->nparts);
   c->d_red = (double*)dalloc(c, sizeof(double) * 8);
-  if (c->geo.open[0] || c->geo.open[1])
-    c->d_side = (double*)dalloc(c, sizeof(double) * 32 * (size_t)p->dims[1] * p->dims[2]);
+  if (open_axis >= 0) {
+    const int t1 = open_axis == 0 ? 1 : 0, t2 = open_axis == 2 ? 1 : 2;
+    c->d_side = (double*)dalloc(c, sizeof(double) * 32 * (size_t)p->dims[t1] * p->dims[t2]);
+  }
     c->d_faceblk = (int*)dalloc(c, sizeof(int) * 2 * (1 + (size_t)nblocks));
   if (!c->grid[0] || !c->grid[1] || !c->d_blocks || !c->d_nbr || !c->d_ghost || !c->d_tasks || !c->d_rim ||
-      !c->d_partial || !c->d_red || ((c->geo.open[0] || c->geo.open[1]) && (!c->d_side || !c->d_faceblk)))
+      !c->d_partial || !c->d_red || (open_axis >= 0 && (!c->d_side || !c->d_faceblk)))
     return bail(LBM_ENOMEM, "device allocation failed");
   if (hipMemcpy(c->d_blocks, c->bh.data(), sizeof(BlockDev) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->nbh.data(), sizeof(NbrDev) * c->nbh.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1322,12 +1337,13 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
                                       hipMemcpyHostToDevice) != hipSuccess))
     return bail(LBM_EDEVICE, "upload of block tables failed");
   if (c->d_faceblk) {
-    // the Blocks touching each open x face
+    // the Blocks touching each open face
     std::vector<int> fl((size_t)2 * (1 + nblocks), 0);
+    const int a = open_axis;
     for (int f = 0; f < 2; ++f)
       for (int j = 0; j < nblocks; ++j) {
         const BlockDev& B = c->bh[j];
-        if (f == 0 ? B.org[0] == 0 : B.org[0] + B.dim[0] == p->dims[0]) {
+        if (f == 0 ? B.org[a] == 0 : B.org[a] + B.dim[a] == p->dims[a]) {
           int* list = fl.data() + (size_t)f * (1 + nblocks);
           list[1 + list[0]] = j;
           ++list[0];
@@ -1348,12 +1364,14 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
 
 lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
-  if (solid && (c->geo.open[0] || c->geo.open[1])) {
+  if (solid && has_open(c)) {
     // the boundary node of an open face extrapolates from a fluid cell
-    const int nx = c->geo.n[0];
-    for (long long r = 0; r < c->n_cells / nx; ++r)
-      if ((c->geo.open[0] && solid[r * nx]) || (c->geo.open[1] && solid[r * nx + nx - 1]))
+    const int a = c->geo.open_axis, nx = c->geo.n[0], ny = c->geo.n[1];
+    for (long long k = 0; k < c->n_cells; ++k) {
+      const int p[3] = {(int)(k % nx), (int)(k / nx % ny), (int)(k / ((long long)nx * ny))};
+      if (solid[k] && ((c->geo.open[2 * a] && p[a] == 0) || (c->geo.open[2 * a + 1] && p[a] == c->geo.n[a] - 1)))
         return fail(LBM_EINVAL, "solid cell on an open face");
+    }
   }
   bool any = false;
   long long nsolid = 0;
@@ -1397,6 +1415,7 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
   c->cur = 0;
   c->steps = 0;
   c->mark_steps = -1;
+  c->set_steps = 0;
   // fluid cells per Block (static load balance)
   for (size_t j = 0; j < c->bh.size(); ++j) {
     const lbm_aabb& A = c->aabb[j];
@@ -1425,6 +1444,7 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const double* rho, const double* u) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 0;
   c->mark_steps = -1;
+  c->set_steps = 0;
   return host_pull(c);
 }
 
@@ -1536,6 +1556,7 @@ lbm_status lbm_macroscopic(lbm_ctx* c, double* rho, double* u, int32_t dst_is_de
 lbm_status lbm_residual(lbm_ctx* c, double* r) {
   if (!c || !r) return fail(LBM_EINVAL, "NULL argument");
   if (c->steps < 2) return fail(LBM_ESTATE, "residual needs >= 2 steps since initialisation");
+  if (c->steps == c->set_steps) return fail(LBM_ESTATE, "residual needs a step since the state was last set");
   double s[6];
   lbm_status st = reduce(c, 1, s);
   if (st != LBM_OK) return st;
@@ -1629,7 +1650,21 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* f, int32_t as_fp64) {
   HIPCHK(hipStreamSynchronize(c->stream));
   c->steps = 1;
   c->mark_steps = -1;
+  c->set_steps = 1;
   return host_pull(c);
+}
+
+lbm_status lbm_average_two_steps(lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (hetero(c)) return fail(LBM_EINVAL, "averaging two steps needs every Block on the GPU");
+  if (c->steps <= c->set_steps)
+    return fail(LBM_ESTATE, "averaging two steps needs a step since the state was last set");
+  launch_average(c->prec, c->grid[c->cur], c->grid[c->cur ^ 1], (long long)c->grid_elems, c->stream);
+  enqueue_fill(c, c->cur, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->set_steps = c->steps;
+  return LBM_OK;
 }
 
 lbm_status lbm_get_schedule(lbm_ctx* c, lbm_schedule* s) {
@@ -1644,7 +1679,7 @@ lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* s) {
   if (!sched_valid(*s, err)) return fail(LBM_EINVAL, err);
   if (s->cells_per_lane == 2 && !vec2_allowed(c))
     return fail(LBM_EINVAL,
-                "two cells per lane need F16S/BF16S (or F32 with FP64 math), even x extents and no open faces");
+                "two cells per lane need F16S/BF16S (or F32 with FP64 math), even x extents and no open x faces");
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   const lbm_schedule old = c->sched;

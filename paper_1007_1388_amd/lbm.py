@@ -75,7 +75,7 @@ class lbm_info(ctypes.Structure):
 # The exported symbols of include/lbm.h, in declaration order.
 SYMBOLS = ["lbm_create_blocks", "lbm_set_geometry", "lbm_set_equilibrium", "lbm_step", "lbm_step_persistent",
            "lbm_step_timed", "lbm_macroscopic", "lbm_residual", "lbm_residual_mark", "lbm_residual_since_mark",
-           "lbm_sums", "lbm_sums_noalloc", "lbm_get_state", "lbm_set_state",
+           "lbm_sums", "lbm_sums_noalloc", "lbm_get_state", "lbm_set_state", "lbm_average_two_steps",
            "lbm_get_schedule", "lbm_set_schedule", "lbm_set_host_blocks", "lbm_step_host_timed",
            "lbm_balance_host_blocks", "lbm_autotune", "lbm_info_get", "lbm_destroy",
            "lbm_strerror", "lbm_last_error", "lbm_bw_probe", "lbm_hbm_probe"]
@@ -114,6 +114,7 @@ def load(path=LIB_PATH):
         "lbm_sums_noalloc": [P, dp, dp],
         "lbm_get_state": [P, P, ctypes.c_int32],
         "lbm_set_state": [P, P, ctypes.c_int32],
+        "lbm_average_two_steps": [P],
         "lbm_get_schedule": [P, ctypes.POINTER(lbm_schedule)],
         "lbm_set_schedule": [P, ctypes.POINTER(lbm_schedule)],
         "lbm_set_host_blocks": [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32],
@@ -236,6 +237,10 @@ def lbm_set_state(ctx, f, as_fp64):
     _check(load().lbm_set_state(ctx, f.ctypes.data, int(as_fp64)), "lbm_set_state")
 
 
+def lbm_average_two_steps(ctx):
+    _check(load().lbm_average_two_steps(ctx), "lbm_average_two_steps")
+
+
 def lbm_get_schedule(ctx):
     s = lbm_schedule()
     _check(load().lbm_get_schedule(ctx, ctypes.byref(s)), "lbm_get_schedule")
@@ -310,10 +315,11 @@ def lbm_hbm_probe(kind, unroll, nontemporal, a_ptr, b_ptr, nbytes, grid, reps, s
 
 def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.0,
                 force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False, stream=None, row_pad=0,
-                open_x=None):
-    """open_x = {"-x" or "+x": ("velocity", (ux, uy, uz)) | ("pressure", rho) |
-    "wall"}: open x faces (non-equilibrium extrapolation); an x face not named
-    keeps what walls[0] says (which must then be True)."""
+                open_x=None, open_faces=None):
+    """open_faces = {face: ("velocity", (ux, uy, uz)) | ("pressure", rho) |
+    "wall"}, faces of one axis ("-x"/"+x", "-y"/"+y" or "-z"/"+z"): open faces
+    (non-equilibrium extrapolation); a face of that axis not named keeps what
+    `walls` says for it (which must then be True).  open_x: the older name."""
     p = lbm_params()
     p.dims[:] = [int(d) for d in dims]
     for k in range(3):
@@ -323,8 +329,8 @@ def make_params(dims, walls=(False, False, False), wall_u=None, tau=0.6, rho0=1.
     for face, vel in (wall_u or {}).items():
         for a in range(3):
             p.wall_u[FACES.index(face)][a] = float(vel[a])
-    for face, spec in (open_x or {}).items():
-        k = {"-x": 0, "+x": 1}[face]
+    for face, spec in dict(open_x or {}, **(open_faces or {})).items():
+        k = FACES.index(face)
         if spec == "wall":
             p.face[k] = LBM_WALL
         elif spec[0] == "velocity":
@@ -378,7 +384,7 @@ class Lattice:
 
     def __init__(self, dims, blocks=None, walls=(False, False, False), wall_u=None, tau=0.6,
                  rho0=1.0, force=(0.0, 0.0, 0.0), precision="f32", fp64_math=False,
-                 stream=None, torch_alloc=True, row_pad=0, open_x=None):
+                 stream=None, torch_alloc=True, row_pad=0, open_x=None, open_faces=None):
         load()
         import torch
         if not torch.cuda.is_available():
@@ -394,7 +400,7 @@ class Lattice:
             blocks = [((0, 0, 0), self.dims)]
         self.blocks = [tuple(map(tuple, b)) for b in blocks]
         self.params = make_params(dims, walls, wall_u, tau, rho0, force, precision, fp64_math, stream,
-                                  row_pad, open_x)
+                                  row_pad, open_x, open_faces)
         self._alloc = None
         if torch_alloc:
             self._alloc = _TorchAllocator(stream)
@@ -475,6 +481,11 @@ class Lattice:
     def set_state(self, f, as_fp64=True):
         dt = np.float64 if as_fp64 else STORAGE_DTYPE[self.precision]
         lbm_set_state(self.ctx, np.ascontiguousarray(f, dtype=dt).reshape((19,) + self.shape), as_fp64)
+
+    def average_two_steps(self):
+        """Replace the state by the mean of this step's and the previous
+        step's (removes period-two components of a state set from outside)."""
+        lbm_average_two_steps(self.ctx)
 
     @property
     def schedule(self):

@@ -9,9 +9,10 @@
 2. Training: the U-Net of surrogate.py on (mask, g_x) -> (u, rho - rho0)/g_x,
    BF16 MFMA kernels, FP32 master weights, Adam, masked MSE on fluid cells.
 3. Use: the prediction sets the initial state (an equilibrium of the
-   predicted rho and u) and the same solver runs to the same residual
-   criterion; `solve` times a run end to end, from rest or from the
-   prediction (inference included).
+   predicted rho and u, stepped once and averaged with the next state, see
+   `start_from`) and the same solver runs to the same residual criterion;
+   `solve` times a run end to end, from rest or from the prediction
+   (inference included).
 
 The solver judges the network: a prediction only sets the initial state, and
 both runs stop on the same residual criterion of the same solver.
@@ -210,6 +211,19 @@ class Trainer:
         return rho, u
 
 
+def start_from(lat, rho, u):
+    """Initial state from predicted fields: their equilibrium, one step, then
+    the mean of the two states (lbm_average_two_steps).  An equilibrium of
+    fields that do not solve the discrete equations excites period-two
+    components that some pore geometries hardly damp (the velocity then keeps
+    a step-to-step oscillation while its two-step mean converges); the mean
+    removes them.  Returns the steps taken (1)."""
+    lat.set_equilibrium(rho, u)
+    lat.step(1)
+    lat.average_two_steps()
+    return 1
+
+
 def solve(gx, solid, trainer=None, tol=TOL, dims=DIMS, check_every=100, max_steps=400_000):
     """One run to the residual criterion, from rest or (trainer given) from
     the network's prediction, timed end to end: inference, initial state,
@@ -221,11 +235,13 @@ def solve(gx, solid, trainer=None, tol=TOL, dims=DIMS, check_every=100, max_step
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = make_lattice(gx, solid, None, dims=dims)
+    n0 = 0
     if trainer is not None:
         d = dict(solid=torch.from_numpy(np.ascontiguousarray(solid).reshape(-1)).cuda(), gx=gx)
         rho_p, u_p = trainer.predict(d)
-        lat.set_equilibrium(rho_p.cpu().numpy().reshape(shape), u_p.cpu().numpy().reshape((3,) + shape))
+        n0 = start_from(lat, rho_p.cpu().numpy().reshape(shape), u_p.cpu().numpy().reshape((3,) + shape))
     (n, _, r), = run_to_steady([lat], check_every=check_every, max_steps=max_steps, tol=tol)
+    n += n0
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     lat.close()

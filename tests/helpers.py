@@ -17,13 +17,14 @@ def gpu_lattice(case, blocks=None, precision="f64", fp64_math=False, **kw):
     from paper_1007_1388_amd import lbm
     return lbm.Lattice(case["dims"], blocks=blocks, walls=case.get("walls", (False, False, False)),
                        wall_u=case.get("wall_u"), tau=case["tau"], force=case.get("force", (0, 0, 0)),
-                       precision=precision, fp64_math=fp64_math, open_x=case.get("open_x"), **kw)
+                       precision=precision, fp64_math=fp64_math, open_x=case.get("open_x"),
+                       open_faces=case.get("open_faces"), **kw)
 
 
 def oracle_lattice(case):
     return oracle.OracleLBM(case["dims"], walls=case.get("walls", (False, False, False)),
                             wall_u=case.get("wall_u"), tau=case["tau"], force=case.get("force", (0, 0, 0)),
-                            open_x=case.get("open_x"))
+                            open_x=case.get("open_x"), open_faces=case.get("open_faces"))
 
 
 def prepare(sim, case):

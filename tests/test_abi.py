@@ -92,8 +92,15 @@ def test_mismatched_faces_and_normal_wall_velocity_rejected():
 def test_open_face_rules_rejected():
     ok = dict(open_x={"-x": ("velocity", (0.01, 0, 0)), "+x": ("pressure", 1.0)})
     p = lbm.make_params((8, 8, 8), walls=(True, False, True), tau=0.7, **ok)
-    p.face[2] = p.face[3] = lbm.LBM_VELOCITY          # open faces are x faces only
+    p.face[2] = p.face[3] = lbm.LBM_VELOCITY          # open faces lie on one axis
     assert _status(p, BOX) == lbm.LBM_EINVAL
+    for ax, walls in (("y", (True, True, False)), ("z", (False, True, True))):
+        p = lbm.make_params((8, 8, 8), walls=walls, tau=0.7,
+                            open_faces={"-" + ax: ("velocity", (0.0, 0.01, 0.0)), "+" + ax: ("pressure", 1.0)})
+        assert _status(p, BOX) != lbm.LBM_EINVAL        # the faces of one axis, any axis
+        p = lbm.make_params((8, 1, 8), walls=walls, tau=0.7, open_faces={"-" + ax: ("pressure", 1.0)})
+        if ax == "y":
+            assert _status(p, [((0, 0, 0), (8, 1, 8))]) == lbm.LBM_EINVAL   # two cells across
     p = lbm.make_params((8, 8, 8), walls=(True, False, True), tau=0.7, open_x={"+x": ("pressure", 0.0)})
     assert _status(p, BOX) == lbm.LBM_EINVAL            # density must be > 0
     p = lbm.make_params((8, 8, 8), walls=(False, False, True), tau=0.7, open_x={"-x": ("pressure", 1.0)})

@@ -298,6 +298,88 @@ def test_shear_wave_decays_at_the_bgk_viscosity():
     assert o.residual() == pytest.approx(1 - np.exp(-rate), rel=3e-3)
 
 
+def _permute_case(perm, dims, walls, wall_u, force, open_faces, solid, rho, u):
+    """The same flow with spatial axis k renamed perm[k] (arrays [z][y][x])."""
+    names = "xyz"
+    inv = [perm.index(j) for j in range(3)]
+    axes = [2 - inv[2 - t] for t in range(3)]
+    vec = lambda v: tuple(v[inv[j]] for j in range(3))
+    face = lambda f: f[0] + names[perm[names.index(f[1])]]
+    spec = lambda sp: (sp[0], vec(sp[1])) if sp[0] == "velocity" else sp
+    u2 = np.empty((3,) + tuple(np.transpose(rho, axes).shape))
+    for k in range(3):
+        u2[perm[k]] = np.transpose(u[k], axes)
+    return dict(dims=vec(dims), walls=vec(walls), wall_u={face(f): vec(v) for f, v in wall_u.items()},
+                force=vec(force), open_faces={face(f): spec(sp) for f, sp in open_faces.items()},
+                solid=np.ascontiguousarray(np.transpose(solid, axes)), rho=np.transpose(rho, axes), u=u2,
+                axes=axes)
+
+
+@pytest.mark.parametrize("perm", [(1, 2, 0), (2, 0, 1)])
+def test_open_faces_on_y_and_z_are_the_x_faces_rotated(perm):
+    # A duct with a velocity inlet (tangential part) and a pressure outlet on
+    # x, a moving wall, a body force, spheres off the open faces and a
+    # perturbed warm start, against the same flow with the axes renamed so
+    # that the open faces are y faces or z faces: the fields agree under the
+    # renaming to rounding (the x case is pinned by the closed forms above).
+    dims = (10, 6, 5)
+    solid = inputs.porous_spheres(dims, target_fraction=0.08, radius=(1, 2), seed=3)
+    solid[:, :, 0] = 0
+    solid[:, :, -1] = 0
+    rho, u = inputs.perturbed_fields(dims, seed=3, drho=1e-3, du=1e-2)
+    u[:, solid == 1] = 0.0
+    a = dict(dims=dims, walls=(True, False, True), wall_u={"-z": (0.01, 0.0, 0.0)}, force=(0.0, 3e-6, 1e-6),
+             open_faces={"-x": ("velocity", (0.03, 0.005, -0.002)), "+x": ("pressure", 1.001)},
+             solid=solid, rho=rho, u=u)
+    b = _permute_case(perm, **a)
+    res = []
+    for c in (a, b):
+        o = oracle.OracleLBM(c["dims"], walls=c["walls"], wall_u=c["wall_u"], tau=0.7, force=c["force"],
+                             open_faces=c["open_faces"])
+        o.set_geometry(c["solid"])
+        o.set_equilibrium(c["rho"], c["u"])
+        o.step(40)
+        res.append(o.macroscopic())
+    (ra, ua), (rb, ub) = res
+    assert np.abs(np.transpose(ra, b["axes"]) - rb).max() < 1e-14
+    for k in range(3):
+        assert np.abs(np.transpose(ua[k], b["axes"]) - ub[perm[k]]).max() < 1e-14
+    assert np.abs(ua).max() > 1e-2
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_open_pressure_faces_on_y_or_z_give_the_exact_channel_flow(axis):
+    # The pressure-driven channel of the x test above along y or along z.
+    n, w, D, g, tau = 20, 10, 1e-5, 2e-7, 0.8
+    dims, walls, force = [1, 1, 1], [False, False, False], [0.0, 0.0, 0.0]
+    cross = 2 if axis == 1 else 0
+    dims[axis], dims[cross] = n, w
+    walls[axis] = walls[cross] = True
+    force[axis] = g
+    ax = "xyz"[axis]
+    o = oracle.OracleLBM(tuple(dims), walls=tuple(walls), tau=tau, force=tuple(force),
+                         open_faces={"-" + ax: ("pressure", 1.0 + D), "+" + ax: ("pressure", 1.0)})
+    o.step(30000)
+    rho, u = o.macroscopic()
+    K = 3 * (g + D / (3 * (n + 1))) / (2 * tau - 1)
+    c = np.arange(w)
+    ref = K * (c + 0.5) * (w - 0.5 - c) + K * (16 * tau * tau - 16 * tau + 1) / 12
+    x = np.arange(n)
+    # arrays are [z][y][x]: move (along, across) to the last two places
+    along, across = 2 - axis, 2 - cross
+    ua = np.moveaxis(u[axis], (across, along), (-2, -1)).reshape(w, n)
+    ra = np.moveaxis(rho, (across, along), (-2, -1)).reshape(w, n)
+    assert np.abs(ua - ref[:, None]).max() < 1e-10 * ref.max()
+    assert np.abs(ra - (1.0 + D * (n - x) / (n + 1))[None, :]).max() < 1e-9 * D
+    assert np.abs(np.delete(u, axis, axis=0)).max() < 1e-7 * ref.max()
+
+
+def test_open_faces_on_two_axes_are_rejected():
+    with pytest.raises(ValueError):
+        oracle.OracleLBM((6, 5, 4), walls=(True, True, False), tau=0.7,
+                         open_faces={"-x": ("pressure", 1.0), "+y": ("pressure", 1.0)})
+
+
 # ------------------------------------------------------------ symmetry ------
 
 def _cavity(n=(8, 8, 8), lid=(0.05, 0, 0), face="+z", steps=200):

@@ -1202,9 +1202,15 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     a.nco = (dy->c + bmw - 1) / bmw;
     a.nci = x->c / 32;
     const long long tiles = 3ll * a.nci * a.nco;
+#ifndef LBM_WGT
+#define LBM_WGT 2048
+#endif
+#ifndef LBM_WGMIN
+#define LBM_WGMIN 8
+#endif
     // about 2048 workgroups in all, at least 8 steps each
-    long long per = (steps * tiles + 2047) / 2048;
-    if (per < 8) per = 8;
+    long long per = (steps * tiles + LBM_WGT - 1) / LBM_WGT;
+    if (per < LBM_WGMIN) per = LBM_WGMIN;
     const long long splits = (steps + per - 1) / per;
     a.steps = (int)steps;
     a.per_wg = (int)per;

@@ -643,7 +643,9 @@ __global__ void __launch_bounds__(256) k_conv_halo(DArgs a) {
 
 // ------------------------------------------------- bwd-weight, 3x3x3 halos
 // dw[co][tap*Cin + ci] += sum_v dy[v][co] * x[src(v, tap)][ci] for 3x3x3
-// kernels with Cin a multiple of 32.  A workgroup owns one kernel plane kd,
+// kernels with Cin a multiple of 32, and (db given) db[co] += sum_v dy[v][co]
+// from the dy tiles already in LDS, by the workgroups of kernel plane 0 and
+// input-channel tile 0 (each dy tile once).  A workgroup owns one kernel plane kd,
 // 32 input channels and BM output channels, i.e. a BM x (9 taps x 32) block
 // of dw, and walks a range of 32-voxel steps of dy (R rows of W' voxels,
 // W' = min(W, 32)).  Per step it stages, in their channels-last order,
@@ -665,6 +667,7 @@ struct WArgs {
   Geo gy;
   unsigned dy_bytes;
   float* dw;
+  float* db;            // bias gradient, or nullptr
   int kpad;
   int wp, r, nhb, nwb;  // step shape: R rows of W' voxels; steps per row block / plane
   int steps, per_wg;    // total steps, steps per workgroup
@@ -811,6 +814,11 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   for (int i = 0; i < NSUB; ++i)
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // bias: thread sums channel b_ch over voxels b_v0 .. b_v0 + 32/BG - 1 of each step
+  constexpr int BG = 256 / BM;
+  const bool do_bias = a.db != nullptr && kd == 0 && ci_t == 0;
+  const int b_ch = tid % BM, b_v0 = (tid / BM) * (32 / BG);
+  float bsum = 0.f;
 
   if (s_begin < s_end) {
     load_step(0u);
@@ -837,6 +845,10 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
         for (int i = 0; i < NSUB; ++i)
           acc[i][kh * 3 + kw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][kh * 3 + kw], 0, 0, 0);
       }
+    if (do_bias) {
+#pragma unroll
+      for (int j = 0; j < 32 / BG; ++j) bsum += __uint_as_float((unsigned)A[(b_v0 + j) * PA + b_ch] << 16);
+    }
     store_step(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -853,6 +865,172 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
 #pragma unroll
       for (int t = 0; t < 9; ++t) atomicAdd(a.dw + (long long)co * a.kpad + (kd * 9 + t) * cin + ci, acc[i][t][q]);
     }
+  if (do_bias && co0 + b_ch < gy.c) atomicAdd(a.db + co0 + b_ch, bsum);
+}
+
+// --------------------------------- bwd-weight, 3x3x3, 8 input channels
+// dw[co][tap*8 + ci] += sum_v dy[v][co] * x[src(v, tap)][ci] for the input
+// layer (8 channels, stride 1): all 27 taps of a 32-output-channel tile in
+// one workgroup, the 216 columns as 14 MFMA column tiles of two taps x 8
+// channels (the last holds tap 26 and zeros).  Per 32-voxel step (R rows of
+// W' voxels, as above) it stages the dy tile [32 voxels][32 channels] and the
+// x halo of the three source planes [3][R+2 rows][W'+2 columns][8 channels];
+// ds_read_b64_tr_b16 takes one address per lane, so each lane of a B
+// fragment points at the tap of its half of the tile's columns, and both
+// operands are transposing LDS reads.  Wave w owns output-channel tile w % 2
+// and column tiles w/2, w/2 + 2, ..., w/2 + 12 (seven MFMA tiles).  With db
+// given every workgroup also sums its dy tiles (each once per channel tile).
+__global__ void __launch_bounds__(256) k_conv_wgrad_c8(WArgs a) {
+  constexpr int BC = 32;                 // output channels per tile
+  constexpr int PA = BC + 8;             // dy tile row pitch (bf16)
+  constexpr int PC = 8;                  // halo cell: 8 channels
+  constexpr int PLANE = 102;             // largest (R+2)(W'+2) over the step shapes
+  constexpr int CELLS = 3 * PLANE;
+  constexpr int ZERO = CELLS * PC;       // a cell of zeros (the missing 28th tap)
+  constexpr int NXP = (CELLS + 255) / 256;
+  constexpr unsigned OOB = 0x80000000u;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][32 * PA];
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][(CELLS + 1) * PC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const Geo gx = a.gx, gy = a.gy;
+  // XCD-aware work index (see k_conv_wgrad_halo)
+  const int total = (int)gridDim.x, L8 = (int)blockIdx.x;
+  const int q8 = total / 8 * 8;
+  const int idx = L8 < q8 ? (L8 % 8) * (total / 8) + L8 / 8 : L8;
+  const int co_t = idx % a.nco, split = idx / a.nco;
+  const int co0 = co_t * BC;
+  const int wp = a.wp, rr = a.r;
+  const int hc = wp + 2, hr = rr + 2, pcells = hr * hc, ncell = 3 * pcells;
+  if (tid < 2 * PC / 8) *(u32x4*)(&Xs[tid][ZERO]) = u32x4{0u, 0u, 0u, 0u};
+
+  // staging roles: dy chunk (voxel, 8-channel group), threads 0..127
+  const bool a_act = tid < 32 * BC / 8;
+  const int a_v = tid / (BC / 8), a_q = tid % (BC / 8);
+  const bool a_on = a_act && co0 + a_q * 8 < gy.c;
+  const int a_r = (a_v & 31) / wp, a_c = (a_v & 31) % wp;
+  // halo cell (plane, row, column)
+  int x_p[NXP], x_hr[NXP], x_hc[NXP];
+  bool x_on[NXP];
+#pragma unroll
+  for (int i = 0; i < NXP; ++i) {
+    const int cell = tid + i * 256;
+    x_on[i] = cell < ncell;
+    x_p[i] = cell / pcells;
+    x_hr[i] = (cell % pcells) / hc;
+    x_hc[i] = cell % hc;
+  }
+  // operand read offsets (16-lane group g covers voxels 8g..8g+7, half h the
+  // rows 8g+4h..+3; lane L addresses row L/4, columns (L%4)*4..+3)
+  const int L = lane & 15, g = lane >> 4;
+  const int cot = wave & 1, kt0 = wave >> 1;
+  const int hi = (L & 3) >> 1, cio = (L & 1) * 4;
+  int aoff[2], xb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int v = 8 * g + 4 * h + (L >> 2);
+    aoff[h] = v * PA + cot * 16 + (L & 3) * 4;
+    xb[h] = ((v / wp) * hc + (v % wp)) * PC + cio;
+  }
+  // per column tile j of this wave: the lane's tap and its halo offset
+  int toff[7];
+  bool tzero[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const int t = 2 * (kt0 + 2 * j) + hi;
+    tzero[j] = t >= 27;
+    const int tt = tzero[j] ? 0 : t;
+    toff[j] = ((tt / 9) * pcells + ((tt / 3) % 3) * hc + tt % 3) * PC;
+  }
+
+  const __amdgpu_buffer_rsrc_t rx = rsrc_of(a.x, a.x_bytes);
+  const __amdgpu_buffer_rsrc_t rd = rsrc_of(a.dy, a.dy_bytes);
+  const int s_begin = split * a.per_wg;
+  const int s_end = s_begin + a.per_wg < a.steps ? s_begin + a.per_wg : a.steps;
+  int st = s_begin;
+  int wb = st % a.nwb, hb = (st / a.nwb) % a.nhb, pl = st / (a.nwb * a.nhb);
+  int nn = pl / gy.d, dd = pl % gy.d;
+  auto advance = [&]() {
+    ++wb;
+    const int c1 = wb == a.nwb;
+    wb = c1 ? 0 : wb;
+    hb += c1;
+    const int c2 = hb == a.nhb;
+    hb = c2 ? 0 : hb;
+    dd += c2;
+    const int c3 = dd == gy.d;
+    dd = c3 ? 0 : dd;
+    nn += c3;
+  };
+  u32x4 ar, xr[NXP];
+  auto load_step = [&](unsigned dead) {
+    const int h0 = hb * rr, w0 = wb * wp;
+    {
+      const int hh = h0 + a_r, ww = w0 + a_c;
+      const bool ok = a_on && hh < gy.h && ww < gy.w;
+      const unsigned vo =
+          (unsigned)((((nn * gy.d + dd) * gy.h + hh) * gy.w + ww) * gy.ldc + co0 + a_q * 8) * 2u | (ok ? 0u : OOB);
+      ar = __builtin_amdgcn_raw_buffer_load_b128(rd, vo | dead, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NXP; ++i) {
+      const int zs = dd + x_p[i] - 1, ys = h0 - 1 + x_hr[i], xs = w0 - 1 + x_hc[i];
+      const bool ok = x_on[i] && zs >= 0 && zs < gx.d && ys >= 0 && ys < gx.h && xs >= 0 && xs < gx.w;
+      const unsigned vo = (unsigned)((((nn * gx.d + zs) * gx.h + ys) * gx.w + xs) * gx.ldc) * 2u | (ok ? 0u : OOB);
+      xr[i] = __builtin_amdgcn_raw_buffer_load_b128(rx, vo | dead, 0, 0);
+    }
+  };
+  auto store_step = [&](int buf) {
+    if (a_act) *(u32x4*)(&As[buf][(a_v & 31) * PA + a_q * 8]) = ar;
+#pragma unroll
+    for (int i = 0; i < NXP; ++i)
+      if (x_on[i]) *(u32x4*)(&Xs[buf][(x_p[i] * pcells + x_hr[i] * hc + x_hc[i]) * PC]) = xr[i];
+  };
+
+  f32x4 acc[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool do_bias = a.db != nullptr;
+  const int b_ch = tid % BC, b_v0 = (tid / BC) * 4;
+  float bsum = 0.f;
+
+  if (s_begin < s_end) {
+    load_step(0u);
+    store_step(0);
+    __syncthreads();
+  }
+  int buf = 0;
+  for (; st < s_end; ++st) {
+    advance();
+    load_step(st + 1 < s_end ? 0u : OOB);
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the MFMAs
+    const uint16_t* A = As[buf];
+    const uint16_t* X = Xs[buf];
+    const bf16x8 af = tr_load8(A, aoff[0], aoff[1]);
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const bf16x8 bfr = tr_load8(X, tzero[j] ? ZERO + cio : xb[0] + toff[j], tzero[j] ? ZERO + cio : xb[1] + toff[j]);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[j], 0, 0, 0);
+    }
+    if (do_bias) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bsum += __uint_as_float((unsigned)A[(b_v0 + j) * PA + b_ch] << 16);
+    }
+    store_step(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // lane holds D[(lane/16)*4 + q][lane%16] of each tile: rows co, columns k
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int co = co0 + cot * 16 + g * 4 + q;
+    if (co >= gy.c) continue;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      const int k = (kt0 + 2 * j) * 16 + L;
+      if (k < 216) atomicAdd(a.dw + (long long)co * a.kpad + k, acc[j][q]);
+    }
+  }
+  if (do_bias && co0 + b_ch < gy.c) atomicAdd(a.db + co0 + b_ch, bsum);
 }
 
 // dbias[co] += sum_v dy[v][co]: a thread sums 8 channels (one 16-byte load
@@ -1192,6 +1370,7 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     a.gy = geo_of(dy);
     a.dy_bytes = (unsigned)view_bytes(dy);
     a.dw = dw;
+    a.db = dbias;
     a.kpad = kpad;
     a.wp = dy->w >= 32 ? 32 : dy->w;
     a.r = 32 / a.wp;
@@ -1202,15 +1381,14 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     a.nco = (dy->c + bmw - 1) / bmw;
     a.nci = x->c / 32;
     const long long tiles = 3ll * a.nci * a.nco;
-#ifndef LBM_WGT
-#define LBM_WGT 2048
-#endif
-#ifndef LBM_WGMIN
-#define LBM_WGMIN 8
-#endif
-    // about 2048 workgroups in all, at least 8 steps each
-    long long per = (steps * tiles + LBM_WGT - 1) / LBM_WGT;
-    if (per < LBM_WGMIN) per = LBM_WGMIN;
+    // About 2048 workgroups in all, and at least 48 voxel steps each: every
+    // workgroup ends with BM x 288 FP32 atomics into dw, which dominate the
+    // layers of few voxels when their work is split finer (measured on
+    // gfx950, batch 8: 16x8x8 256->256 0.170 -> 0.115 ms, 32x16x16 128->128
+    // 0.186 -> 0.158 ms; the full-resolution layers already take 96-384
+    // steps per workgroup and lose with fewer workgroups).
+    long long per = (steps * tiles + 2047) / 2048;
+    if (per < 48) per = 48;
     const long long splits = (steps + per - 1) / per;
     a.steps = (int)steps;
     a.per_wg = (int)per;
@@ -1226,11 +1404,34 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
       else
         hipLaunchKernelGGL((k_conv_wgrad_halo<2, 64>), g, b, 0, s, a);
     }
-    if (dbias) {
-      const long long pb = 2048;
-      hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((V + pb - 1) / pb)), b, 0, s, (const uint16_t*)dy->ptr,
-                         geo_of(dy), dbias, pb);
-    }
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+  }
+  if (ksize == 3 && stride == 1 && x->c == 8 && wfit && tap_fits(x) && tap_fits(dy) && V < (1ll << 31)) {
+    WArgs a{};
+    a.x = (const uint16_t*)x->ptr;
+    a.gx = geo_of(x);
+    a.x_bytes = (unsigned)view_bytes(x);
+    a.dy = (const uint16_t*)dy->ptr;
+    a.gy = geo_of(dy);
+    a.dy_bytes = (unsigned)view_bytes(dy);
+    a.dw = dw;
+    a.db = dbias;
+    a.kpad = kpad;
+    a.wp = dy->w >= 32 ? 32 : dy->w;
+    a.r = 32 / a.wp;
+    a.nhb = (dy->h + a.r - 1) / a.r;
+    a.nwb = (dy->w + a.wp - 1) / a.wp;
+    const long long steps = (long long)dy->n * dy->d * a.nhb * a.nwb;
+    a.nco = (dy->c + 31) / 32;
+    a.nci = 1;
+    // about 1024 workgroups, at least 48 steps each (each ends with 32 x 216
+    // FP32 atomics)
+    long long per = (steps * a.nco + 1023) / 1024;
+    if (per < 48) per = 48;
+    const long long splits = (steps + per - 1) / per;
+    a.steps = (int)steps;
+    a.per_wg = (int)per;
+    hipLaunchKernelGGL(k_conv_wgrad_c8, dim3((unsigned)(splits * a.nco)), b, 0, s, a);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
   }
   const int gm = (dy->c + BM - 1) / BM, gn = (kpad + 63) / 64;

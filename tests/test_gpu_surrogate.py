@@ -56,6 +56,16 @@ CASES = [
     dict(n=1, d=3, h=8, w=64, ci=64, co=32, k=3, s=1),
     dict(n=1, d=4, h=7, w=32, ci=64, co=64, k=3, s=1),
     dict(n=1, d=4, h=5, w=32, ci=96, co=48, k=3, s=1),
+    # weight gradient of the 8-channel input layer (all 27 taps per
+    # workgroup): rows of 16, 32 + a partial 8 and 2 voxels per step, one to
+    # two output-channel tiles (partial ones included)
+    dict(n=2, d=5, h=6, w=16, ci=8, co=32, k=3, s=1),
+    dict(n=1, d=4, h=5, w=40, ci=8, co=48, k=3, s=1),
+    dict(n=1, d=3, h=7, w=2, ci=8, co=16, k=3, s=1),
+    # pointwise products: 16 to 64 input channels, partial output-channel
+    # tiles
+    dict(n=1, d=3, h=5, w=9, ci=64, co=8, k=1, s=1),
+    dict(n=1, d=2, h=7, w=13, ci=16, co=24, k=1, s=1),
 ]
 
 

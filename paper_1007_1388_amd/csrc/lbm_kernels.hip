@@ -346,7 +346,10 @@ __device__ __forceinline__ double open_corr(const GridGeom& g, int side, int q, 
 // every wall link; with FUSED the boundary values also go
 // straight into the neighbours' ghost layers (the on-GPU copies of Sec. 4.4,
 // fused into the sweep).
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
+// FORCE = false (16-bit storage without a body force): the force terms,
+// all zero, are left out of the collision (the storage formats' sweeps are
+// bound by instruction issue, not bytes).
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN, bool FORCE = true>
 __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& ph_in, const void* src_grid, void* dst_grid,
                                           const BlockDev& B_in, int bid, int z, int y0w, int x0w, int yend, int xw,
                                           const GhostTgt* gts) {
@@ -608,7 +611,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
       uz[k] = fma(jz, pp->inv_rho0, pp->hg[2]);
     }
     uu15[k] = (C)1.5 * fma(ux[k], ux[k], fma(uy[k], uy[k], uz[k] * uz[k]));
-    ug3[k] = pp->rho0x3 * fma(ux[k], pp->g[0], fma(uy[k], pp->g[1], uz[k] * pp->g[2]));
+    if constexpr (FORCE)
+      ug3[k] = pp->rho0x3 * fma(ux[k], pp->g[0], fma(uy[k], pp->g[1], uz[k] * pp->g[2]));
+    else
+      ug3[k] = (C)0;
   }
 
   // stores of direction i; solid cells store zero (no cell reads their
@@ -767,8 +773,13 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
     for (int k = 0; k < VEC; ++k) {
       // rest: feq~_0 = w0 (drho + rho0 (-1.5 u.u)), F_0 = w0 rho0 (-3 u.g)
       const C feq = pp->w[0] * fma(pp->rho0, -uu15[k], drho[k]);
-      const C F = -pp->w[0] * ug3[k];
-      const C even = fma(pp->omega, feq, pp->fcoef * F);
+      C even;
+      if constexpr (FORCE) {
+        const C F = -pp->w[0] * ug3[k];
+        even = fma(pp->omega, feq, pp->fcoef * F);
+      } else {
+        even = pp->omega * feq;
+      }
       if constexpr (HYB)
         o[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[0][k]), (double)even));
       else
@@ -801,15 +812,20 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
       }
       // even part (shared by i and its opposite) and odd part (flips sign)
       const C sym = pp->w[WCLS(i)] * fma(pp->rho0, fma((C)4.5 * eu, eu, -uu15[k]), drho[k]);
-      const C Fs = fma(pp->c9g[i], eu, -pp->w[WCLS(i)] * ug3[k]);
-      const C even = fma(pp->omega, sym, pp->fcoef * Fs);
+      C even;
+      if constexpr (FORCE) {
+        const C Fs = fma(pp->c9g[i], eu, -pp->w[WCLS(i)] * ug3[k]);
+        even = fma(pp->omega, sym, pp->fcoef * Fs);
+      } else {
+        even = pp->omega * sym;
+      }
       if constexpr (HYB) {
         const double odd = fma(pp->domega, pp->dc3w[WCLS(i)] * deu, pp->dcfa[i]);
         const double ev = (double)even;
         o0[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[i][k]), ev + odd));
         o1[k] = from_c<PREC, double>(fma(pp->domc, (double)to_c<PREC, C>(W[i + 1][k]), ev - odd));
       } else {
-        const C odd = fma(pp->omega, pp->c3w[WCLS(i)] * eu, pp->cfa[i]);
+        const C odd = FORCE ? fma(pp->omega, pp->c3w[WCLS(i)] * eu, pp->cfa[i]) : pp->omega * (pp->c3w[WCLS(i)] * eu);
         o0[k] = from_c<PREC, C>(fma(pp->omc, to_c<PREC, C>(W[i][k]), even + odd));
         o1[k] = from_c<PREC, C>(fma(pp->omc, to_c<PREC, C>(W[i + 1][k]), even - odd));
       }
@@ -861,7 +877,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
 // The work items of one sweep from src to dst, workgroup by workgroup
 // (item w, w + grid, ...); the waves of a workgroup take an item's
 // (row group, 64-lane segment) tasks in turn.
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN, bool FORCE = true>
 __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& ph, const void* src, void* dst,
                                             GhostTgt* gts) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -881,7 +897,7 @@ __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& p
       const int ntask = (item.nrows * a + 63) >> 6;
       for (int t = wv; t < ntask; t += nw) {
         const int f = t * 64, ry = f / a;
-        sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + ry,
+        sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN, FORCE>(A, ph, src, dst, B, item.block, item.z, item.y0 + ry,
                                                     f - ry * a, yend, 0, gts);
       }
       continue;
@@ -895,7 +911,7 @@ __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& p
     const int ntask = ngroups * nseg;
     for (int t = wv; t < ntask; t += nw) {
       const int grp = t / nseg, seg = t - grp * nseg;
-      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, src, dst, B, item.block, item.z, item.y0 + grp * rpw,
+      sweep_row<PREC, C, MASK, FX, NT, VEC, OPEN, FORCE>(A, ph, src, dst, B, item.block, item.z, item.y0 + grp * rpw,
                                                   seg * 64 * VEC, yend, xw, gts);
     }
   }
@@ -903,12 +919,12 @@ __device__ __forceinline__ void sweep_items(const SweepArgs& A, const Phys<C>& p
 
 // At least 4 (one cell per lane) or 3 (two cells per lane) waves per SIMD.
 // OPEN: contexts with open x faces (one cell per lane).
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN, bool FORCE = true>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VEC > 1 ? 3 : 4)))
 k_sweep(const SweepArgs A, const Phys<C> ph) {
   // ghost targets of the current item's Block (fused exchange)
   __shared__ GhostTgt gts[FX == 1 ? 27 : 1];
-  sweep_items<PREC, C, MASK, FX, NT, VEC, OPEN>(A, ph, A.src, A.dst, gts);
+  sweep_items<PREC, C, MASK, FX, NT, VEC, OPEN, FORCE>(A, ph, A.src, A.dst, gts);
 }
 
 // Several steps in one launch: a persistent block-list kernel.  Every
@@ -1420,12 +1436,12 @@ __global__ void __launch_bounds__(256) k_copy16(const u32x4* __restrict__ src, u
 // ------------------------------------------------------------- launchers
 using SweepFn = void (*)(SweepArgs, Phys<double>, Phys<float>, dim3, dim3, hipStream_t);
 
-template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN = false>
+template <int PREC, typename C, bool MASK, int FX, bool NT, int VEC, bool OPEN = false, bool FORCE = true>
 static void launch_sweep_t(SweepArgs a, Phys<double> pd, Phys<float> pf, dim3 g, dim3 b, hipStream_t s) {
   if constexpr (sizeof(C) == 8)
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN>), g, b, 0, s, a, pd);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN, FORCE>), g, b, 0, s, a, pd);
   else
-    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN>), g, b, 0, s, a, pf);
+    hipLaunchKernelGGL((k_sweep<PREC, C, MASK, FX, NT, VEC, OPEN, FORCE>), g, b, 0, s, a, pf);
 }
 
 // Contexts with open faces: one cell per lane, non-temporal (the cache hint
@@ -1444,10 +1460,15 @@ static SweepFn pick_open(bool mask, int fx) {
 #undef LBM_PICK
 }
 
+// force = false picks the force-free collision for 16-bit storage with
+// streaming stores (measured on gfx950, 384^3 cavity: FP16S sweep 0.905 ->
+// 0.851 ms; FP32 and FP64, bound by bytes, gain nothing)
 template <int PREC, typename C, int VEC>
-static SweepFn pick3(bool mask, int fx, bool nt) {
-#define LBM_PICK(M, F) \
-  return nt ? launch_sweep_t<PREC, C, M, F, true, VEC> : launch_sweep_t<PREC, C, M, F, false, VEC>
+static SweepFn pick3(bool mask, int fx, bool nt, bool force) {
+#define LBM_PICK(M, F)                                                                                    \
+  return nt ? (PREC >= 2 && !force ? launch_sweep_t<PREC, C, M, F, true, VEC, false, PREC <= 1>          \
+                                   : launch_sweep_t<PREC, C, M, F, true, VEC>)                            \
+            : launch_sweep_t<PREC, C, M, F, false, VEC>
   if (mask) {
     if (fx == 1) LBM_PICK(true, 1);
     if (fx == 2) LBM_PICK(true, 2);
@@ -1463,7 +1484,7 @@ static SweepFn pick3(bool mask, int fx, bool nt) {
 // per lane and stream, like FP32) and FP32 storage with FP64 arithmetic.
 bool sweep_vec2_ok(int prec, bool f64math) { return prec >= 2 || (prec == 1 && f64math); }
 
-void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, bool force, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s) {
   SweepFn fn = nullptr;
   const bool v = vec == 2 && sweep_vec2_ok(prec, f64math);
@@ -1478,13 +1499,13 @@ void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, c
     return;
   }
   switch (prec) {
-    case 0: fn = pick3<0, double, 1>(mask, fx, nt); break;
+    case 0: fn = pick3<0, double, 1>(mask, fx, nt, force); break;
     case 1:
-      if (f64math) fn = v ? pick3<1, double, 2>(mask, fx, nt) : pick3<1, double, 1>(mask, fx, nt);
-      else fn = pick3<1, float, 1>(mask, fx, nt);
+      if (f64math) fn = v ? pick3<1, double, 2>(mask, fx, nt, force) : pick3<1, double, 1>(mask, fx, nt, force);
+      else fn = pick3<1, float, 1>(mask, fx, nt, force);
       break;
-    case 2: fn = v ? pick3<2, float, 2>(mask, fx, nt) : pick3<2, float, 1>(mask, fx, nt); break;
-    default: fn = v ? pick3<3, float, 2>(mask, fx, nt) : pick3<3, float, 1>(mask, fx, nt); break;
+    case 2: fn = v ? pick3<2, float, 2>(mask, fx, nt, force) : pick3<2, float, 1>(mask, fx, nt, force); break;
+    default: fn = v ? pick3<3, float, 2>(mask, fx, nt, force) : pick3<3, float, 1>(mask, fx, nt, force); break;
   }
   fn(a, pd, pf, grid, block, s);
 }

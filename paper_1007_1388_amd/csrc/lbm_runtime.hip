@@ -25,7 +25,7 @@
 #include "lbm_internal.h"
 
 namespace lbm {
-void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, int vec, const SweepArgs& a,
+void launch_sweep(int prec, bool f64math, bool mask, int fx, bool nt, bool force, int vec, const SweepArgs& a,
                   const Phys<double>& pd, const Phys<float>& pf, dim3 grid, dim3 block, hipStream_t s);
 bool sweep_vec2_ok(int prec, bool f64math);
 hipError_t launch_sweep_steps(int prec, bool f64math, bool mask, const SweepArgs& a, const Phys<double>& pd,
@@ -554,7 +554,8 @@ void enqueue_sweep(lbm_ctx* c, int from, hipStream_t s) {
   int grid = nitems;
   if (c->sched.persistent > 0) grid = std::min(nitems, c->sched.persistent * c->cu_count);
   if (grid < 1) grid = 1;
-  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange, c->sched.nontemporal != 0,
+  const bool force = c->p.force[0] != 0.0 || c->p.force[1] != 0.0 || c->p.force[2] != 0.0;
+  launch_sweep(c->prec, c->f64math, c->has_mask, c->sched.fused_exchange, c->sched.nontemporal != 0, force,
                cells_per_lane(c, c->sched), a, c->phd, c->phf, dim3(grid), dim3(c->sched.wg_size), s);
 }
 

@@ -127,6 +127,25 @@ def test_shifted_half_storage_tracks_oracle(precision, tol, dims):
     assert err["u_inf"] < tol, err
 
 
+@pytest.mark.parametrize("precision", ["f16s", "bf16s"])
+def test_force_free_half_storage_bitwise_across_tilings(precision):
+    """Without a body force the 16-bit sweeps leave the (zero) force terms
+    out of the collision (the test above checks them against the oracle):
+    tilings, exchange modes and two cells per lane give the one-Block result
+    bit for bit."""
+    dims = (24, 12, 10)
+    case = cavity(dims=dims, lid=(0.05, 0.0, 0.0))
+    case["solid"] = inputs.porous_spheres(dims, target_fraction=0.05, radius=(1, 2), seed=9,
+                                          periodic=(False, False, False))
+    ref = run_gpu(case, 30, precision=precision).get_state(as_fp64=False)
+    for split, sched in [((2, 2, 1), None), ((3, 1, 2), dict(fused_exchange=1)), (None, dict(cells_per_lane=2)),
+                         ((2, 2, 1), dict(cells_per_lane=2, fused_exchange=0))]:
+        blocks = inputs.uniform_blocks(dims, split) if split else None
+        lat = run_gpu(case, 30, blocks=blocks, precision=precision, schedule=sched)
+        assert np.array_equal(lat.get_state(as_fp64=False), ref)
+        lat.close()
+
+
 def test_porous_multiblock_f64_matches_oracle():
     dims = (40, 24, 20)
     solid = inputs.porous_spheres(dims, target_fraction=0.15, radius=(2, 4), seed=5)

@@ -152,14 +152,19 @@ typedef struct {
  * it crosses); BlockID = index in `blocks`.  Block data live on the device;
  * the management data (AABB, BlockID, neighbour table) is also kept on the
  * host (Sec. 4.2).  State after creation: all fluid, rest equilibrium
- * f~ = 0.  Errors: LBM_EINVAL (bad parameters or tiling), LBM_ENOMEM,
- * LBM_EDEVICE.  *out is set only on success. */
+ * f~ = 0.  Errors: LBM_EINVAL (bad parameters or tiling, or a Block one
+ * of whose population arrays, ghost layers included, would reach 4 GiB:
+ * about 530 M cells in FP64, 1070 M in FP32), LBM_ENOMEM, LBM_EDEVICE.
+ * *out is set only on success. */
 lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_t nblocks,
                              lbm_ctx** out);
 
 /* Solid mask on the host, nx*ny*nz bytes, x fastest, nonzero = solid;
  * NULL = all fluid.  Builds the per-cell link masks for half-way bounce-back
- * at obstacles (Sec. 2.1) and resets the state to rest (f~ = 0). */
+ * at obstacles (Sec. 2.1) and resets the state to rest (f~ = 0).
+ * LBM_EINVAL for a solid cell on an open face, or for obstacles in a Block
+ * six of whose population arrays would reach 4 GiB (about 89 M cells in
+ * FP64, 178 M in FP32, 357 M in 16-bit storage). */
 lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid);
 
 /* Warm start: f~ = feq~(rho - rho0, u) of Eq. (2) in every fluid cell, 0 in

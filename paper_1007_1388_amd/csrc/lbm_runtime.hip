@@ -1227,15 +1227,15 @@ lbm_status lbm_create_blocks(const lbm_params* p, const lbm_aabb* blocks, int32_
     off = roundup(B.base + (long long)kQ * B.Sf, 4096 / c->sbytes);
     B.mask = -1;
   }
-  // The sweep addresses a Block's arrays through buffer resources that each
-  // cover up to five population arrays (plus 32-bit row and lane offsets):
-  // six arrays of a Block, ghost layers included, must stay below 4 GiB.
+  // The sweep addresses a row by a scalar base plus 32-bit offsets that
+  // reach across one population array (its x-ghost plane included), so one
+  // array of a Block must stay below 4 GiB; the obstacle variants' buffer
+  // resources span six arrays (checked when obstacles are set).
   for (const auto& B : c->bh)
-    if (6LL * B.Sf * c->sbytes >= 0xFFFFFFF0LL) {
+    if ((long long)B.Sf * c->sbytes >= 0xFFFFFFF0LL) {
       lbm_destroy(c);
-      return fail(LBM_EINVAL, "Block too large: six population arrays of a Block (ghost layers included) "
-                              "must stay below 4 GiB (at most about 89 M cells in FP64, 178 M in FP32, "
-                              "357 M in 16-bit storage)");
+      return fail(LBM_EINVAL, "Block too large: one population array of a Block (ghost layers included) "
+                              "must stay below 4 GiB (about 530 M cells in FP64, 1070 M in FP32)");
     }
   c->grid_elems = (size_t)off;
   c->x_even = true;
@@ -1381,6 +1381,12 @@ lbm_status lbm_set_geometry(lbm_ctx* c, const uint8_t* solid) {
       if (solid[k]) ++nsolid;
     any = nsolid > 0;
   }
+  if (any)
+    for (const auto& B : c->bh)
+      if (6LL * B.Sf * c->sbytes >= 0xFFFFFFF0LL)
+        return fail(LBM_EINVAL, "Block too large for obstacles: six population arrays of a Block (ghost layers "
+                                "included) must stay below 4 GiB (about 89 M cells in FP64, 178 M in FP32, "
+                                "357 M in 16-bit storage)");
   drop_graphs(c);
   if (any) {
     if (!c->d_mask) {

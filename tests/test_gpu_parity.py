@@ -468,6 +468,28 @@ def test_packed_rows_are_layout_only(precision, dims, split):
     assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
 
 
+def test_block_size_limits():
+    """A Block one of whose FP64 population arrays would reach 4 GiB is
+    refused before anything is allocated; a 512^3 FP64 Block (1.1 GB per
+    array) runs, and refuses obstacles, whose addressing spans six arrays."""
+    import torch
+    from paper_1007_1388_amd import lbm
+    with pytest.raises(lbm.LBMError):
+        lbm.Lattice((1100, 1100, 1100), precision="f64", tau=0.7)
+    lat = lbm.Lattice((512, 512, 512), walls=(False, False, True), precision="f64", tau=0.7,
+                      force=(1e-6, 0.0, 0.0))
+    solid = np.zeros(lat.shape, np.uint8)
+    solid[5, 6, 7] = 1
+    with pytest.raises(lbm.LBMError):
+        lat.set_geometry(solid)
+    lat.step(3)
+    mass, mom = lat.sums()
+    assert abs(mass - 512 ** 3) < 1e-6 * 512 ** 3 and mom[0] > 0
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------ sums, residual ----
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

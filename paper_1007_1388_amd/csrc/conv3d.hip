@@ -684,17 +684,23 @@ __device__ __forceinline__ bf16x8 tr_load8(const uint16_t* p, int off_lo, int of
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-template <int S, int BM>
+// VS = 64 or 128 (stride 1, rows of at least 32 voxels): steps of two or
+// four 32-voxel rows, each tap's K chunks run on one staging of dy and of
+// the halo of VS/32 + 2 rows, so a barrier and a staging round cover two or
+// four times the MFMAs.
+template <int S, int BM, int VS = 32>
 __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   constexpr int PA = BM + 8;                 // dy tile row pitch (bf16)
   constexpr int PC = 40;                     // halo cell pitch: 32 channels + 8
-  constexpr int CELLS = S == 1 ? 102 : 195;  // largest halo over the step shapes
-  constexpr int NAC = 32 * BM / 8;           // dy chunks of 8 channels
+  // largest halo over the step shapes (VS >= 64: rows of 32 voxels only)
+  constexpr int CELLS = VS >= 64 ? ((VS / 32 - 1) * S + 3) * (31 * S + 3) : (S == 1 ? 102 : 195);
+  constexpr int NK = VS / 32;                // 32-voxel K chunks per step
+  constexpr int NAC = VS * BM / 8;           // dy chunks of 8 channels
   constexpr int NAP = (NAC + 255) / 256;
   constexpr int NXP = (CELLS * 4 + 255) / 256;
   constexpr int NSUB = BM / 32;              // 16-row output tiles per wave
   constexpr unsigned OOB = 0x80000000u;
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][32 * PA];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][VS * PA];
   __shared__ __attribute__((aligned(16))) uint16_t Xs[2][CELLS * PC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const Geo gx = a.gx, gy = a.gy;
@@ -730,8 +736,8 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   int a_r[NAP], a_c[NAP];
 #pragma unroll
   for (int i = 0; i < NAP; ++i) {
-    a_r[i] = (a_v[i] & 31) / wp;
-    a_c[i] = (a_v[i] & 31) % wp;
+    a_r[i] = (a_v[i] & (VS - 1)) / wp;
+    a_c[i] = (a_v[i] & (VS - 1)) % wp;
   }
   // halo chunk (cell, channel group)
   int x_hr[NXP], x_hc[NXP], x_q[NXP];
@@ -803,7 +809,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   auto store_step = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < NAP; ++i)
-      if (tid + i * 256 < NAC) *(u32x4*)(&As[buf][(a_v[i] & 31) * PA + a_q[i] * 8]) = ar[i];
+      if (tid + i * 256 < NAC) *(u32x4*)(&As[buf][(a_v[i] & (VS - 1)) * PA + a_q[i] * 8]) = ar[i];
 #pragma unroll
     for (int i = 0; i < NXP; ++i)
       if (x_on[i]) *(u32x4*)(&Xs[buf][(x_hr[i] * hc + x_hc[i]) * PC + x_q[i] * 8]) = xr[i];
@@ -817,7 +823,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
   // bias: thread sums channel b_ch over voxels b_v0 .. b_v0 + 32/BG - 1 of each step
   constexpr int BG = 256 / BM;
   const bool do_bias = a.db != nullptr && kd == 0 && ci_t == 0;
-  const int b_ch = tid % BM, b_v0 = (tid / BM) * (32 / BG);
+  const int b_ch = tid % BM, b_v0 = (tid / BM) * (VS / BG);
   float bsum = 0.f;
 
   if (s_begin < s_end) {
@@ -832,22 +838,27 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_halo(WArgs a) {
     __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the MFMAs
     const uint16_t* A = As[buf];
     const uint16_t* X = Xs[buf];
-    bf16x8 af[NSUB];
+    // K chunk c: voxels 32c..32c+31 of the step (with VS = 64 the second
+    // 32-voxel row: dy rows +32, halo rows +1)
 #pragma unroll
-    for (int i = 0; i < NSUB; ++i) af[i] = tr_load8(A, aoff[i][0], aoff[i][1]);
+    for (int c = 0; c < NK; ++c) {
+      bf16x8 af[NSUB];
 #pragma unroll
-    for (int kh = 0; kh < 3; ++kh)
+      for (int i = 0; i < NSUB; ++i) af[i] = tr_load8(A, aoff[i][0] + c * 32 * PA, aoff[i][1] + c * 32 * PA);
 #pragma unroll
-      for (int kw = 0; kw < 3; ++kw) {
-        const int to = (kh * hc + kw) * PC;
-        const bf16x8 bfr = tr_load8(X, xoff[0] + to, xoff[1] + to);
+      for (int kh = 0; kh < 3; ++kh)
 #pragma unroll
-        for (int i = 0; i < NSUB; ++i)
-          acc[i][kh * 3 + kw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][kh * 3 + kw], 0, 0, 0);
-      }
+        for (int kw = 0; kw < 3; ++kw) {
+          const int to = (kh * hc + kw) * PC + c * S * hc * PC;
+          const bf16x8 bfr = tr_load8(X, xoff[0] + to, xoff[1] + to);
+#pragma unroll
+          for (int i = 0; i < NSUB; ++i)
+            acc[i][kh * 3 + kw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr, acc[i][kh * 3 + kw], 0, 0, 0);
+        }
+    }
     if (do_bias) {
 #pragma unroll
-      for (int j = 0; j < 32 / BG; ++j) bsum += __uint_as_float((unsigned)A[(b_v0 + j) * PA + b_ch] << 16);
+      for (int j = 0; j < VS / BG; ++j) bsum += __uint_as_float((unsigned)A[(b_v0 + j) * PA + b_ch] << 16);
     }
     store_step(buf ^ 1);
     __syncthreads();
@@ -1372,8 +1383,11 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     a.dw = dw;
     a.db = dbias;
     a.kpad = kpad;
+    // steps of several 32-voxel rows with rows of 32 voxels or more
+    const bool vs64 = dy->w >= 32;
+    const int vs = !vs64 ? 32 : (stride == 2 ? 64 : 128);
     a.wp = dy->w >= 32 ? 32 : dy->w;
-    a.r = 32 / a.wp;
+    a.r = vs / a.wp;
     a.nhb = (dy->h + a.r - 1) / a.r;
     a.nwb = (dy->w + a.wp - 1) / a.wp;
     const long long steps = (long long)dy->n * dy->d * a.nhb * a.nwb;
@@ -1388,12 +1402,22 @@ lbm_status lbm_conv3d_bwd_weight(const lbm_tensor5* x, const lbm_tensor5* dy, fl
     // 0.186 -> 0.158 ms; the full-resolution layers already take 96-384
     // steps per workgroup and lose with fewer workgroups).
     long long per = (steps * tiles + 2047) / 2048;
-    if (per < 48) per = 48;
+    if (per < 48 * 32 / vs) per = 48 * 32 / vs;
     const long long splits = (steps + per - 1) / per;
     a.steps = (int)steps;
     a.per_wg = (int)per;
     const dim3 g((unsigned)(splits * tiles));
-    if (stride == 1) {
+    if (vs64 && stride == 1) {
+      if (bmw == 32)
+        hipLaunchKernelGGL((k_conv_wgrad_halo<1, 32, 128>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_conv_wgrad_halo<1, 64, 128>), g, b, 0, s, a);
+    } else if (vs64) {
+      if (bmw == 32)
+        hipLaunchKernelGGL((k_conv_wgrad_halo<2, 32, 64>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_conv_wgrad_halo<2, 64, 64>), g, b, 0, s, a);
+    } else if (stride == 1) {
       if (bmw == 32)
         hipLaunchKernelGGL((k_conv_wgrad_halo<1, 32>), g, b, 0, s, a);
       else

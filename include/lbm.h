@@ -85,7 +85,7 @@ typedef struct {
   int32_t dims[3];        /* nx, ny, nz of the single Patch, each >= 1 */
   int32_t face[6];        /* lbm_face of -x,+x,-y,+y,-z,+z: both faces of an axis
                              PERIODIC, or each WALL, VELOCITY or PRESSURE (the
-                             last two on x faces only) */
+                             last two on the faces of one axis only) */
   double wall_u[6][3];    /* WALL faces: wall velocity, tangential; VELOCITY faces: the
                              prescribed velocity (any direction); 0 on other faces */
   double tau;             /* BGK relaxation time, > 0.5 (nu = (tau - 1/2)/3) */

@@ -164,6 +164,11 @@ __device__ __forceinline__ void buf_store(T* base, uint32_t boff, T v) {
 __host__ __device__ constexpr int GRP0(int i) { return i < 5 ? 0 : (i < 9 ? 5 : (i < 13 ? 9 : (i < 17 ? 13 : 17))); }
 constexpr int kGroups = 5;
 __host__ __device__ constexpr int GRPI(int i) { return i < 5 ? 0 : (i < 9 ? 1 : (i < 13 ? 2 : (i < 17 ? 3 : 4))); }
+// Sector of a row's last line that the padding lanes of the sweep complete
+// (measured on gfx950, FP32 periodic cubes: 32-byte sectors lift 255^3 from
+// 31.3k to 35.0k MLUPS, 64-byte sectors 257^3 too, 31.6k -> 32.6k, and 200^3,
+// 30.3k -> 32.0k; whole 128-byte lines add more write traffic than they save)
+constexpr int kPadSector = 64;
 constexpr uint32_t kRange = 0xFFFFFFF0u;  // records of a group resource; an offset of kRange reads zero
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t grp_rsrc(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)kRange, 0x00020000);
@@ -394,7 +399,23 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   const int y = y0w + r;
   // Lanes of a live row all take part in the shuffles; a lane only reads a
   // neighbour lane of its own live row.
-  if (x0 >= a || y >= yend) return;
+  // Padding lanes (one cell per lane, rows padded past a): the lanes past
+  // the row's last cell up to the end of its last 64-byte sector store into
+  // the row padding, so that the row's last line is not written in part
+  // (the memory then merges the partial sector by a read-modify-write: a
+  // row of 255 FP32 cells took 12 % longer than one of 256 with the same
+  // traffic).  Their values go to the padding only, which no cell reads;
+  // no wall, face or exchange rule applies to them, and with obstacles they
+  // take the solid-cell path (no loads, zeros stored).  Otherwise their
+  // pulls read slots next to their own (the row's last line, or slot Sx,
+  // the next row's first), or, with 16-bit storage, their own slots
+  // (measured per variant on gfx950: the select costs the FP32 sweep 0.7 %
+  // and gains the F16S sweep 1.3 %).
+  const int pend = VEC == 1 && xw != 0
+                       ? min(B.Sx, (a * (int)sizeof(T) + kPadSector - 1) / kPadSector * kPadSector / (int)sizeof(T))
+                       : a;
+  if (x0 >= pend || y >= yend) return;
+  const bool pad = x0 >= a;
 
   // The group resources and scalar row offsets of the one-cell-per-lane
   // addressing are rebuilt for every row from the Block's base and strides
@@ -434,9 +455,10 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
     solid[k] = false;
   }
   if constexpr (MASK) {
-    const uint32_t* mp = pa->mask + B.mask + ((long long)z * b + y) * a + x0;
+    const uint32_t* mp = pa->mask + B.mask + ((long long)z * b + y) * a + (pad ? 0 : x0);
 #pragma unroll
     for (int k = 0; k < VEC; ++k) m[k] = mp[k];
+    if (pad) m[0] = kSolidBit;
     if constexpr (VEC == 1) solid[0] = (m[0] & kSolidBit) != 0;
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -489,6 +511,9 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
       uint32_t off = lob + (uint32_t)((1 - ex) * (int)sizeof(T));
       if (ex > 0) off = xg_lo ? xlo : off;
       if (ex < 0) off = xg_hi ? xhi : off;
+      if constexpr (PREC >= 2) {
+        if (ex != 0) off = pad ? lob + S1 : off;
+      }
       W[i][0] = ldo<T>(pr, off);
     } else {
       T V[VEC];
@@ -573,6 +598,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   wf.hiy = pa->geo.fwall[3] && gy == pa->geo.n[1] - 1;
   wf.loz = pa->geo.fwall[4] && gz == 0;
   wf.hiz = pa->geo.fwall[5] && gz == pa->geo.n[2] - 1;
+  if (pad) wf.lox = wf.hix = wf.loy = wf.hiy = wf.loz = wf.hiz = false;
   const bool moving = pa->geo.moving[0] | pa->geo.moving[1] | pa->geo.moving[2] | pa->geo.moving[3] | pa->geo.moving[4] |
                       pa->geo.moving[5];
 
@@ -694,7 +720,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   const int ylast = min(y0w + (xw ? 64 / xw : (x0w + 63) / a + 1), yend) - 1;
   const bool yz_face = (z == 0) | (z == c - 1) | (y0w == 0) | (ylast >= b - 1);
   constexpr bool FUSED = FX == 1;
-  const bool edge = FUSED && yz_face &&
+  const bool edge = FUSED && yz_face && !pad &&
                     ((x0 == 0) | (x0 + VEC - 1 == a - 1) | (y == 0) | (y == b - 1) | (z == 0) | (z == c - 1));
   // x-ghost slot of row y for direction q: base + q * Sf (wave-uniform) plus
   // the lane's row offset within the wave
@@ -725,7 +751,7 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   // at most one face cell.
   double* sp = nullptr;
   int sdir = 0;  // e_x of the populations that enter through the lane's face
-  if (OPEN && pa->side != nullptr) {
+  if (OPEN && pa->side != nullptr && !pad) {
     const long long cell = (long long)gz * pa->geo.n[1] + gy;
     if (pa->geo.open[0] && gx0 == 0) {
       sp = pa->side + 16 * cell;

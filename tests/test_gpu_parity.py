@@ -468,6 +468,55 @@ def test_packed_rows_are_layout_only(precision, dims, split):
     assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
 
 
+def _pad_case(kind):
+    dims = (104, 12, 10)
+    if kind == "open":
+        return duct(dims=dims, seed=4)
+    solid = inputs.porous_spheres(dims, target_fraction=0.08, radius=(2, 3), seed=4)
+    rho, u = inputs.perturbed_fields(dims, seed=4, drho=1e-3, du=1e-2)
+    u[:, solid == 1] = 0.0
+    return dict(dims=dims, walls=(True, False, True), wall_u={"+x": (0.0, 0.01, 0.0), "-z": (0.01, 0.0, 0.0)},
+                tau=0.7, force=(2e-6, 1e-6, 0.0), init=(rho, u), solid=solid)
+
+
+# a Block of 100 cells along x next to one of 4: padding lanes of the first
+# (x = 100 .. 103 in FP64, .. 111 in FP32, .. 127 in F16S) lie at global x up
+# to and past the far x face of the 104-cell domain
+PAD_SPLIT = [((0, 0, 0), (100, 6, 10)), ((100, 0, 0), (104, 6, 10)), ((0, 6, 0), (100, 12, 10)),
+             ((100, 6, 0), (104, 12, 10))]
+
+
+@pytest.mark.parametrize("kind", ["walls", "open"])
+def test_padding_lanes_write_only_padding(kind):
+    """The lanes past a row's end that complete its last 64-byte sector
+    write only row padding, and the wall, open-face and exchange rules never
+    fire for them although their global x reaches the far x face (x walls
+    with a moving +x wall, or a velocity inlet and pressure outlet):
+    obstacles (padding lanes take the solid-cell path) and a body force.
+    FP64 against the oracle; FP32 and F16S bit for bit across tilings, every
+    exchange mode, row paddings and (closed faces) the persistent sweep."""
+    case = _pad_case(kind)
+    check_vs_oracle(run_gpu(case, 25, blocks=PAD_SPLIT), run_oracle(case, 25), TOL["f64"])
+    for precision in ("f32", "f16s"):
+        runs = [(None, 0, {}), (PAD_SPLIT, 0, dict(fused_exchange=0)), (PAD_SPLIT, 0, dict(fused_exchange=1)),
+                (PAD_SPLIT, 0, dict(fused_exchange=2, graph_steps=5)), (PAD_SPLIT, -1, {}), (PAD_SPLIT, 2, {})]
+        if kind == "walls":
+            runs.append((PAD_SPLIT, 0, "persistent"))
+        states = []
+        for blocks, row_pad, sched in runs:
+            lat = gpu_lattice(case, blocks=blocks, precision=precision, row_pad=row_pad)
+            prepare(lat, case)
+            if sched == "persistent":
+                lat.step_persistent(25, steps_per_launch=10)
+            else:
+                lat.set_schedule(**sched)
+                lat.step(25)
+            states.append(lat.get_state(as_fp64=False))
+            lat.close()
+        for st in states[1:]:
+            assert np.array_equal(st, states[0])
+
+
 def test_block_size_limits():
     """A Block one of whose FP64 population arrays would reach 4 GiB is
     refused before anything is allocated; a 512^3 FP64 Block (1.1 GB per

@@ -104,7 +104,8 @@ typedef struct {
                              Blocks with an even y extent, packed two rows to three
                              128-byte lines); -1 = every row rounded up to 128 bytes;
                              n > 0 = rounded up, then n more 128-byte lines (layout only;
-                             results do not depend on it) */
+                             results do not depend on it; the sweep may store into the
+                             padding, whose contents no call reads or returns) */
   double face_rho[6];     /* PRESSURE faces: the prescribed density (> 0); ignored
                              on other faces */
 } lbm_params;

@@ -366,11 +366,14 @@ __device__ __forceinline__ void sweep_row(const SweepArgs& A_in, const Phys<C>& 
   // hoisted above these points.
   // Which of these help was measured per kernel variant on gfx950 (same
   // box, A/B): reading the arguments at the point of use pays for every
-  // variant but the 16-bit ones without obstacles; laundering the Block's
-  // layout values, for FP32 and FP64 storage without obstacles; the
-  // scalar-offset buffer addressing below, for the obstacle variants (the
-  // porous channel's sweep 1.165 -> 1.108 ms; the others lose 1-2 % with it).
-  constexpr bool KARGS = !(PREC >= 2 && !MASK);
+  // variant but the 16-bit ones without obstacles that apply a body force
+  // (without one, 16-bit cavity sweep 0.835 -> 0.831 ms F16S, 0.841 ->
+  // 0.833 ms BF16S); laundering the Block's layout values, for FP32 and
+  // FP64 storage without obstacles (the force-free 16-bit sweeps lose 5 %
+  // with it); the scalar-offset buffer addressing below, for the obstacle
+  // variants (the porous channel's sweep 1.165 -> 1.108 ms; the others lose
+  // 1-2 % with it).
+  constexpr bool KARGS = !(PREC >= 2 && !MASK && FORCE);
   constexpr bool BLAUNDER = !MASK && PREC <= 1;
   constexpr bool ADDR = MASK && VEC == 1;
   auto ka = ArgPtrs<KARGS, C>::get(A_in, ph_in);

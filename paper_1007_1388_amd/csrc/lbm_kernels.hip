@@ -1006,44 +1006,61 @@ __global__ void __launch_bounds__(256) k_exchange(T* __restrict__ grid, const Bl
                                                   const NbrDev* __restrict__ nbr,
                                                   const XchgTask* __restrict__ tasks, int ntasks,
                                                   T* __restrict__ buf = nullptr) {
-  // one workgroup per task; a thread copies every crossing direction of its
-  // ghost cell, all loads before the stores
+  // one workgroup per task; a thread copies every crossing direction of up
+  // to kXU of the task's ghost cells (cells l, l + 256, ...), all loads
+  // before the stores, so that up to 5 kXU loads per lane are in flight (a
+  // task holds at most 1024 cells)
+  constexpr int kXU = 4;
   for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
     const XchgTask t = tasks[task];
     const BlockDev M = blocks[t.dst];
     const NbrDev nb = nbr[t.dst * 27 + t.d];
     const BlockDev N = blocks[nb.id];
     const bool xplane = t.lo[0] < 0 || t.lo[0] >= M.dim[0];
-    for (int L = t.l0 + threadIdx.x; L < t.l1; L += blockDim.x) {
-      const int q0 = L % t.ext[0];
-      const int r = L / t.ext[0];
-      const int q1 = r % t.ext[1];
-      const int q2 = r / t.ext[1];
-      const int gx = t.lo[0] + q0, gy = t.lo[1] + q1, gz = t.lo[2] + q2;
-      const int sx = gx + nb.tx, sy = gy + nb.ty, sz = gz + nb.tz;
-      T v[5];
-      bool ok[5];
+    for (int L0 = t.l0 + threadIdx.x; L0 < t.l1; L0 += kXU * blockDim.x) {
+      T v[kXU][5];
+      bool ok[kXU][5];
+      int g[kXU][3];
 #pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        const int i = (t.dirs >> (5 * j)) & 31;
-        // only slots whose puller (g + e_i, folded on the axes the Block
-        // wraps on) lies inside the receiving Block
-        int px = gx + kEx[i], py = gy + kEy[i], pz = gz + kEz[i];
-        if (M.wrap & 1) px = px < 0 ? px + M.dim[0] : (px >= M.dim[0] ? px - M.dim[0] : px);
-        if (M.wrap & 2) py = py < 0 ? py + M.dim[1] : (py >= M.dim[1] ? py - M.dim[1] : py);
-        if (M.wrap & 4) pz = pz < 0 ? pz + M.dim[2] : (pz >= M.dim[2] ? pz - M.dim[2] : pz);
-        ok[j] = j < t.ndir && px >= 0 && px < M.dim[0] && py >= 0 && py < M.dim[1] && pz >= 0 && pz < M.dim[2];
-        const long long bi = (long long)t.bo + 5ll * (L - t.l0) + j;
-        if (ok[j]) v[j] = MODE == 2 ? buf[bi] : grid[main_off(N, i, sx, sy, sz)];
+      for (int u = 0; u < kXU; ++u) {
+        const int L = L0 + u * (int)blockDim.x;
+        const bool live = L < t.l1;
+        const int q0 = L % t.ext[0];
+        const int r = L / t.ext[0];
+        const int q1 = r % t.ext[1];
+        const int q2 = r / t.ext[1];
+        const int gx = t.lo[0] + q0, gy = t.lo[1] + q1, gz = t.lo[2] + q2;
+        g[u][0] = gx;
+        g[u][1] = gy;
+        g[u][2] = gz;
+        const int sx = gx + nb.tx, sy = gy + nb.ty, sz = gz + nb.tz;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const int i = (t.dirs >> (5 * j)) & 31;
+          // only slots whose puller (g + e_i, folded on the axes the Block
+          // wraps on) lies inside the receiving Block
+          int px = gx + kEx[i], py = gy + kEy[i], pz = gz + kEz[i];
+          if (M.wrap & 1) px = px < 0 ? px + M.dim[0] : (px >= M.dim[0] ? px - M.dim[0] : px);
+          if (M.wrap & 2) py = py < 0 ? py + M.dim[1] : (py >= M.dim[1] ? py - M.dim[1] : py);
+          if (M.wrap & 4) pz = pz < 0 ? pz + M.dim[2] : (pz >= M.dim[2] ? pz - M.dim[2] : pz);
+          ok[u][j] = live && j < t.ndir && px >= 0 && px < M.dim[0] && py >= 0 && py < M.dim[1] && pz >= 0 &&
+                     pz < M.dim[2];
+          const long long bi = (long long)t.bo + 5ll * (L - t.l0) + j;
+          if (ok[u][j]) v[u][j] = MODE == 2 ? buf[bi] : grid[main_off(N, i, sx, sy, sz)];
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        const int i = (t.dirs >> (5 * j)) & 31;
-        if (!ok[j]) continue;
-        if (MODE == 1)
-          buf[(long long)t.bo + 5ll * (L - t.l0) + j] = v[j];
-        else
-          grid[xplane ? xg_off(M, i, gy, gz) : main_off(M, i, gx, gy, gz)] = v[j];
+      for (int u = 0; u < kXU; ++u) {
+        const int L = L0 + u * (int)blockDim.x;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const int i = (t.dirs >> (5 * j)) & 31;
+          if (!ok[u][j]) continue;
+          if (MODE == 1)
+            buf[(long long)t.bo + 5ll * (L - t.l0) + j] = v[u][j];
+          else
+            grid[xplane ? xg_off(M, i, g[u][1], g[u][2]) : main_off(M, i, g[u][0], g[u][1], g[u][2])] = v[u][j];
+        }
       }
     }
   }

@@ -109,6 +109,26 @@ def test_self_wrapping_host_block():
         ref.close()
 
 
+@pytest.mark.parametrize("fused", [0, 2])
+def test_host_blocks_with_faces_of_many_cells(fused):
+    """Faces of 960 cells (40 x 24), so that every lane of the copy kernel
+    moves four ghost cells of a task, on the GPU side of a host/GPU pair
+    (pack and unpack through the exchange buffer) and between GPU Blocks;
+    FP32 bit for bit against the all-GPU run, FP64 against the oracle."""
+    dims = (96, 40, 24)
+    case = porous(dims=dims, seed=8)
+    blocks = inputs.uniform_blocks(dims, (3, 1, 1))
+    ref = run(case, 9, blocks, precision="f32", fused=fused)
+    lat = run(case, 9, blocks, (1,), precision="f32", fused=fused)
+    assert same_state(lat, ref)
+    f64 = run(case, 9, blocks, (2,), fused=fused)
+    o = run_oracle(case, 9)
+    rho_g, u_g = f64.macroscopic()
+    rho_o, u_o = o.macroscopic()
+    err = field_errors(rho_g, u_g, rho_o, u_o)
+    assert err["u_inf"] <= 1e-12 and err["drho_inf"] <= 1e-12, err
+
+
 def test_moving_blocks_between_host_and_gpu_midrun():
     """The split can change between steps: state carried over exactly,
     diagnostics (sums, residual) equal to the all-GPU run at each stage."""

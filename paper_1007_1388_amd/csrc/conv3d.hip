@@ -1234,12 +1234,15 @@ void launch_tap(const DArgs& a, long long rows, int nz, hipStream_t s) {
 }
 
 // tile shape by output columns: 32 -> 64 rows x 32 per wave, 64 -> 32 x 64,
-// more -> 32 x 128 per column tile
+// more -> 32 x 128 per column tile, or 32 x 64 where 128-column tiles would
+// leave the chip short of workgroups (fewer than two per compute unit: the
+// 16x8x8 layers of 256 channels)
 template <int MODE, bool CLS>
 void launch_tap_cols(const DArgs& a, long long rows, int nz, hipStream_t s) {
+  const long long wide = (rows + 127) / 128 * ((a.go.c + 127) / 128) * nz;
   if (a.go.c <= 32)
     launch_tap<MODE, CLS, 4, 2>(a, rows, nz, s);
-  else if (a.go.c <= 64)
+  else if (a.go.c <= 64 || wide < 512)
     launch_tap<MODE, CLS, 2, 4>(a, rows, nz, s);
   else
     launch_tap<MODE, CLS, 2, 8>(a, rows, nz, s);
